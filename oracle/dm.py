@@ -1,0 +1,175 @@
+"""Dual messenger Wiener filter for (I, Q, U) -> (T, E, B) on the sphere
+(oracle; test infrastructure only).
+
+Follows the paper step by step (Kodi Ramanah, Lavaux & Wandelt 2018):
+
+* eq 4 / Algorithm 1: the messenger covariance T = alpha 1 with alpha the
+  smallest noise eigenvalue.  On a grid with quadrature weights w_p the
+  harmonic-space messenger variance is tau = min_p (alpha_p w_p) and the
+  pixel-space one T_p = tau / w_p (for HEALPix, w = 4 pi / N_pix and
+  tau = alpha w is the sphere's counterpart of sigma^-1 alpha);
+* eq 8 with the Heaviside truncation of the signal covariance (text after
+  eq 9): per ell, in the eigenbasis of the 3x3 block S_l (eq 10),
+      u = (S_bar + U)(S_bar + xi)^-1 t_hat,  S_bar + U = max(S_j, mu),
+      xi = mu + tau,
+  i.e. the filter max(S_j, mu) / (max(S_j, mu) + tau);
+* eq 9, rewritten without N_bar^-1 (which also covers the N_bar = 0 corner
+  case of Sec. 2.1):  t = u_x + T N^-1 (d - u_x) = K u_x + b,
+  K = 1 - T N^-1, b = T N^-1 d, with N^-1 = 0 in masked pixels;
+* Algorithm 1's loop: t_0 = d; each iteration is  t_hat = A t,
+  u = F^mu t_hat, u_x = Y u, t = K u_x + b;  xi is cooled geometrically
+  until mu = 0.  The cooling uses lambda_k = xi_k / tau, geometric from
+  lambda_0 down to exactly 1 over the given number of steps, with a fixed
+  number of iterations per step;
+* diagnostics: the Cauchy ratio of Algorithm 1's stopping rule, the residual
+  ||A x - y|| / ||y|| with A = 1 + S^1/2 N^-1 S^1/2 (Appendix C; here
+  x = S^-1/2 u, y = S^1/2 Y^T N^-1 d) and the chi^2 of eq 3;
+* constrained realizations, eq 19: s_CR = W(d - d_hat) + s_hat.
+"""
+
+import numpy as np
+
+from .geometry import pixel_weights
+from .sht import alm_dot, lm_arrays
+
+
+# ----------------------------------------------------------------------------
+# setup (eq 4, Algorithm 1 initialisation)
+# ----------------------------------------------------------------------------
+def setup(grid, ncov, obs, d):
+    """ncov [3, npix] per-pixel (II, QQ, UU) variances, obs [npix] bool,
+    d [..., 3, npix].  Returns dict(tau, K [3, npix], b [..., 3, npix],
+    ninv [3, npix], d0 = d with the mask zeroed)."""
+    w = pixel_weights(grid)
+    obs = np.ones(grid["npix"], dtype=bool) if obs is None else np.asarray(obs, dtype=bool)
+    alpha_p = np.min(ncov, axis=0)                 # smallest eigenvalue of N_p
+    tau = float(np.min(alpha_p[obs] * w[obs]))
+    ninv = np.where(obs[None, :], 1.0 / np.where(obs[None, :], ncov, 1.0), 0.0)
+    Tp = tau / w
+    K = 1.0 - Tp[None, :] * ninv
+    d0 = np.where(obs, d, 0.0)
+    b = Tp * ninv * d0
+    return dict(tau=tau, K=K, b=b, ninv=ninv, d0=d0, obs=obs)
+
+
+# ----------------------------------------------------------------------------
+# per-ell filters (eq 8 with the Heaviside truncation)
+# ----------------------------------------------------------------------------
+def signal_blocks(cl):
+    """cl [4, lmax+1] in the order TT, EE, BB, TE -> (S2 [l, 2, 2], BB [l])."""
+    TT, EE, BB, TE = cl
+    S2 = np.stack([np.stack([TT, TE], -1), np.stack([TE, EE], -1)], -2)
+    return S2, BB
+
+
+def matrix_function(cl, fn):
+    """Apply a scalar function to the eigenvalues of each S_l (eq 10):
+    returns (FTT, FTE, FEE, FBB)."""
+    S2, BB = signal_blocks(cl)
+    vals, vecs = np.linalg.eigh(S2)
+    fv = fn(vals)
+    M = np.einsum("lij,lj,lkj->lik", vecs, fv, vecs)
+    return M[:, 0, 0], M[:, 0, 1], M[:, 1, 1], fn(BB)
+
+
+def messenger_filter(cl, mu, tau):
+    """F_l = R^T diag(max(S_j, mu) / (max(S_j, mu) + tau)) R."""
+    return matrix_function(cl, lambda s: np.maximum(s, mu) / (np.maximum(s, mu) + tau))
+
+
+def apply_blocks(F, a, lmax):
+    """u = F a per (l, m) with the 3x3 (TE block + B) matrix of each l."""
+    FTT, FTE, FEE, FBB = F
+    ls, _ = lm_arrays(lmax)
+    u = np.empty_like(a)
+    u[0] = FTT[ls] * a[0] + FTE[ls] * a[1]
+    u[1] = FTE[ls] * a[0] + FEE[ls] * a[1]
+    u[2] = FBB[ls] * a[2]
+    return u
+
+
+def schedule(lambda0, nsteps):
+    """lambda_k = lambda0^(1 - k/(K-1)), k = 0..K-1; the last one is 1."""
+    if nsteps <= 1:
+        return np.ones(max(nsteps, 1))
+    k = np.arange(nsteps)
+    lam = float(lambda0) ** (1.0 - k / (nsteps - 1))
+    lam[-1] = 1.0
+    return lam
+
+
+# ----------------------------------------------------------------------------
+# the iteration (Algorithm 1)
+# ----------------------------------------------------------------------------
+def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False):
+    """Run the dual messenger loop.  Returns dict(u [3, nalm], ux = Y u
+    [3, npix], tau, cauchy (last), trace (list of per-iteration cauchy))."""
+    lmax = sht.lmax
+    st = setup(sht.grid, ncov, obs, d)
+    tau, K, b = st["tau"], st["K"], st["b"]
+    t = st["d0"].copy()
+    u_prev = None
+    cauchy = []
+    u = ux = None
+    for lam in schedule(lambda0, nsteps):
+        mu = (lam - 1.0) * tau
+        F = messenger_filter(cl, mu, tau)
+        for _ in range(iters_per_step):
+            t_hat = sht.analysis(t)
+            u = apply_blocks(F, t_hat, lmax)
+            ux = sht.synthesis(u)
+            t = K * ux + b
+            if u_prev is not None:
+                cauchy.append(cauchy_ratio(u, u_prev, lmax))
+            u_prev = u
+    return dict(u=u, ux=ux, tau=tau, cauchy=cauchy[-1] if cauchy else float("nan"),
+                trace=cauchy if trace else None, setup=st)
+
+
+# ----------------------------------------------------------------------------
+# diagnostics (Appendix C residual, eq 3 chi^2)
+# ----------------------------------------------------------------------------
+def residual(sht, u, d, ncov, obs, cl, ux=None):
+    """||A x - y|| / ||y||, A = 1 + S^1/2 Y^T N^-1 Y S^1/2, x = S^+1/2 u,
+    y = S^1/2 Y^T N^-1 d (pseudo-inverse on the zero modes of S)."""
+    lmax = sht.lmax
+    st = setup(sht.grid, ncov, obs, d)
+    ninv, d0 = st["ninv"], st["d0"]
+    if ux is None:
+        ux = sht.synthesis(u)
+    half = matrix_function(cl, lambda s: np.sqrt(np.maximum(s, 0.0)))
+    ihalf = matrix_function(cl, lambda s: np.where(s > 0, 1.0 / np.sqrt(np.where(s > 0, s, 1.0)), 0.0))
+    r = apply_blocks(ihalf, u, lmax) + apply_blocks(half, sht.adjoint(ninv * (ux - d0)), lmax)
+    y = apply_blocks(half, sht.adjoint(ninv * d0), lmax)
+    nr = sum(alm_dot(r[f], r[f], lmax) for f in range(3))
+    ny = sum(alm_dot(y[f], y[f], lmax) for f in range(3))
+    return float(np.sqrt(nr / ny))
+
+
+def chi2(sht, u, d, ncov, obs, cl, ux=None):
+    """(d - Y u)^T N^-1 (d - Y u) + u^dagger S^+ u."""
+    lmax = sht.lmax
+    st = setup(sht.grid, ncov, obs, d)
+    if ux is None:
+        ux = sht.synthesis(u)
+    res = st["d0"] - ux
+    sinv = matrix_function(cl, lambda s: np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0))
+    su = apply_blocks(sinv, u, lmax)
+    return float(np.sum(res * res * st["ninv"]) + sum(alm_dot(u[f], su[f], lmax) for f in range(3)))
+
+
+def cauchy_ratio(u, u_prev, lmax):
+    """||u_i - u_{i-1}|| / ||u_i||, harmonic L2 over T, E, B (Algorithm 1's
+    stopping rule, applied to the iterate u)."""
+    num = sum(alm_dot(u[f] - u_prev[f], u[f] - u_prev[f], lmax) for f in range(3))
+    den = sum(alm_dot(u[f], u[f], lmax) for f in range(3))
+    return float(np.sqrt(num / den)) if den > 0 else 0.0
+
+
+# ----------------------------------------------------------------------------
+# constrained realizations (eq 19)
+# ----------------------------------------------------------------------------
+def constrained_realization(sht, d, dhat, shat, ncov, obs, cl, lambda0, nsteps, iters):
+    """s_CR = W(d - d_hat) + s_hat, one messenger run on d - d_hat."""
+    r = solve(sht, d - dhat, ncov, obs, cl, lambda0, nsteps, iters)
+    return r["u"] + shat

@@ -1,0 +1,106 @@
+"""Pins of the oracle's Wigner-d / spin-weighted Legendre functions against
+routes that share nothing with its recurrence: SciPy's spherical harmonics,
+the Goldberg et al. (1967) explicit finite sum, closed forms at l = 2, the
+addition theorem (which exercises the underflow rescaling at high order) and
+the conjugation identity."""
+
+import numpy as np
+import pytest
+from scipy.special import sph_harm_y
+
+from oracle.harmonics import spin_lambda, goldberg_sylm, wigner_d
+
+THETAS = np.array([1e-3, 0.05, 0.3, 1.1, np.pi / 2, 2.0, 2.9, np.pi - 0.02])
+
+
+def test_spin0_matches_scipy():
+    lmax = 14
+    ms = np.arange(-lmax, lmax + 1)
+    lam = spin_lambda(lmax, 0, THETAS, ms)
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            ref = sph_harm_y(l, m, THETAS, 0.0).real
+            assert np.allclose(lam[:, l, m + lmax], ref, rtol=0, atol=5e-14)
+    # entries with |m| > l vanish
+    for l in range(lmax + 1):
+        assert np.all(lam[:, l, np.abs(ms) > l] == 0)
+
+
+@pytest.mark.parametrize("s", [2, -2, 1, -1])
+def test_spin_matches_goldberg_sum(s):
+    lmax = 10
+    th = THETAS[1:-1]              # the explicit sum loses digits at the poles
+    ms = np.arange(-lmax, lmax + 1)
+    lam = spin_lambda(lmax, s, th, ms)
+    for l in range(abs(s), lmax + 1):
+        for m in range(-l, l + 1):
+            ref = goldberg_sylm(s, l, m, th, 0.0)
+            assert np.allclose(lam[:, l, m + lmax], ref.real, rtol=0, atol=1e-12)
+            assert np.all(np.abs(ref.imag) < 1e-12)
+    assert np.all(lam[:, :abs(s), :] == 0)
+
+
+def test_spin2_closed_forms_at_l2():
+    th = THETAS
+    ms = np.arange(-2, 3)
+    lam = spin_lambda(2, 2, th, ms)
+    c = np.cos(th)
+    s = np.sin(th)
+    assert np.allclose(lam[:, 2, 2], np.sqrt(15 / (32 * np.pi)) * s ** 2, atol=1e-15)
+    assert np.allclose(lam[:, 2, 3], -np.sqrt(5 / (16 * np.pi)) * s * (1 - c), atol=1e-15)
+    assert np.allclose(lam[:, 2, 1], -np.sqrt(5 / (16 * np.pi)) * s * (1 + c), atol=1e-15)
+    assert np.allclose(lam[:, 2, 4], np.sqrt(5 / (64 * np.pi)) * (1 - c) ** 2, atol=1e-15)
+    assert np.allclose(lam[:, 2, 0], np.sqrt(5 / (64 * np.pi)) * (1 + c) ** 2, atol=1e-15)
+
+
+def test_wigner_small_closed_forms():
+    th = THETAS
+    d1 = wigner_d(1, 0, th, [-1, 0, 1])
+    assert np.allclose(d1[:, 1, 1], np.cos(th), atol=1e-15)
+    assert np.allclose(d1[:, 1, 2], -np.sin(th) / np.sqrt(2), atol=1e-15)    # d^1_{1,0}
+    assert np.allclose(d1[:, 1, 0], np.sin(th) / np.sqrt(2), atol=1e-15)     # d^1_{-1,0}
+    d2 = wigner_d(2, 2, th, [2])
+    assert np.allclose(d2[:, 2, 0], np.cos(th / 2) ** 4, atol=1e-15)
+
+
+@pytest.mark.parametrize("s", [0, 2, -2])
+def test_addition_theorem_high_l(s):
+    """sum_m |sY_lm|^2 = (2l+1)/(4 pi) at every l up to 2048, on a polar
+    HEALPix-like ring (sin theta ~ 8e-4), where edge values underflow, plus
+    two other colatitudes.  The three-term recurrence loses about l^2 eps near
+    the pole (4e-11 relative at l = 2048, m = 0, against an 80-bit
+    recurrence), hence the 1e-10 bound; a wrong term gives O(1) errors."""
+    lmax = 2048
+    th = np.array([np.arccos(1 - 1 / (3 * 1024.0 ** 2)), 0.7, np.pi / 2])
+    ms = np.arange(-lmax, lmax + 1)
+    lam = spin_lambda(lmax, s, th, ms)
+    tot = np.sum(lam ** 2, axis=2)
+    ell = np.arange(lmax + 1)
+    want = (2 * ell + 1) / (4 * np.pi)
+    want[: abs(s)] = 0
+    assert np.allclose(tot, want[None, :], rtol=1e-10, atol=0)
+
+
+def test_conjugation_identity():
+    """sY*_lm = (-1)^(s+m) (-s)Y_l,-m  ->  for the real functions
+    slam_lm = (-1)^(s+m) (-s)lam_l,-m."""
+    lmax = 40
+    ms = np.arange(-lmax, lmax + 1)
+    for s in (0, 1, 2):
+        a = spin_lambda(lmax, s, THETAS, ms)
+        b = spin_lambda(lmax, -s, THETAS, ms)[:, :, ::-1]
+        sign = ((-1.0) ** (s + ms))[None, None, :]
+        assert np.allclose(a, sign * b, atol=1e-13)
+
+
+def test_north_south_parity():
+    """slam_lm(pi - theta) = (-1)^(l+m) (-s)lam_lm(theta)."""
+    lmax = 30
+    ms = np.arange(-lmax, lmax + 1)
+    th = THETAS[1:-1]
+    for s in (0, 2):
+        a = spin_lambda(lmax, s, np.pi - th, ms)
+        b = spin_lambda(lmax, -s, th, ms)
+        ell = np.arange(lmax + 1)
+        sign = (-1.0) ** (ell[:, None] + ms[None, :])
+        assert np.allclose(a, sign[None] * b, atol=1e-13)
