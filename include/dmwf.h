@@ -1,0 +1,203 @@
+/*
+ * dmwf.h -- C ABI of the dual messenger Wiener filter for CMB (I, Q, U) maps
+ * on the sphere, for AMD MI355X (gfx950).
+ *
+ * Method: Kodi Ramanah, Lavaux & Wandelt (2018), "Optimal and fast E/B
+ * separation with a dual messenger field".  The library solves the Wiener
+ * filter equation (S^-1 + N^-1) s = N^-1 d (Sec. 1, eq 2) for joint
+ * temperature and polarization data with the dual messenger iteration
+ * (Sec. 2, eqs 8-9 and Algorithm 1), and produces constrained realizations
+ * (Sec. 2.2, eq 19).  The paper's flat-sky FFT basis change (eqs 12-16) is
+ * replaced by spin-0 + spin-2 spherical harmonic transforms on an
+ * iso-latitude ring grid (HEALPix RING or Gauss-Legendre).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Maps      [nrhs][3][npix] doubles, fields (I, Q, U), pixels in RING order
+ *           (rings from north to south, pixel j of a ring at
+ *           phi = phi0 + 2 pi j / nphi).
+ * alm       [nrhs][3][nalm][2] doubles, fields (T, E, B), interleaved
+ *           complex (re, im), only m >= 0, packed m-major:
+ *           idx(l, m) = m (2 lmax + 1 - m) / 2 + l, nalm = (lmax+1)(lmax+2)/2.
+ *           Fields are real: a_{l,-m} = (-1)^m conj(a_lm).  E and B are zero
+ *           for l < 2.
+ * Harmonics Y_lm with the Condon-Shortley phase; spin-2 harmonics in the
+ *           Goldberg et al. (1967) convention; polarization in the
+ *           Zaldarriaga-Seljak (1997) convention:
+ *           Q +- iU = sum_lm (+-2)a_lm (+-2)Y_lm, (+-2)a = -(a^E +- i a^B).
+ * Transforms Y = alm2map (synthesis); Y^T = its plain adjoint (no weights,
+ *           for sum_{l, m=-l..l} conj(a) b on coefficients and the real dot
+ *           product on maps); A = Y^T W = map2alm with W the pixel
+ *           quadrature weights (4 pi / npix on HEALPix).
+ * Ownership The caller owns every buffer it passes.  Host-pointer calls copy
+ *           inputs to the device and results back before returning.
+ *           *_device calls borrow caller device buffers for the duration of
+ *           the work they enqueue on the given HIP stream (NULL = the null
+ *           stream) and return once it is enqueued.  The plan owns all other
+ *           device memory.
+ * Threads   A plan is not thread-safe: use it from one host thread at a time.
+ * Errors    Every call returns dm_status (0 = DM_OK).  On error nothing is
+ *           written to outputs unless stated; dm_last_error() describes the
+ *           last error on that plan.  No C++ exception crosses this ABI.
+ */
+#ifndef DMWF_H
+#define DMWF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMWF_ABI_VERSION 1
+
+typedef enum {
+    DM_OK = 0,
+    DM_EINVAL = -1,        /* invalid argument or input data            */
+    DM_ENOMEM = -2,        /* device or host allocation failed          */
+    DM_EDEVICE = -3,       /* no usable GPU, or a HIP runtime error     */
+    DM_ENONFINITE = -4,    /* a non-finite value appeared in the iterate */
+    DM_ESTATE = -5,        /* call out of order (e.g. no noise set yet)  */
+    DM_EUNSUPPORTED = -6   /* valid request that this build cannot run   */
+} dm_status;
+
+typedef enum { DM_GRID_HEALPIX_RING = 0, DM_GRID_GAUSS_LEGENDRE = 1 } dm_grid_kind;
+
+/* DM_FP64: every step in double precision.
+ * DM_MIXED: Legendre recursion, seeds and rescaling in double precision;
+ *           harmonic-coefficient contraction and the ring-Fourier data in
+ *           single precision; the iterate alm and the final residual in
+ *           double precision.  I/O buffers are always double.            */
+typedef enum { DM_FP64 = 0, DM_MIXED = 1 } dm_precision;
+
+/* Per-pixel noise covariance layout.  DM_NCOV_DIAG3: [3][npix] variances
+ * (II, QQ, UU), i.e. N_p diagonal (eq 11 with vanishing cross terms).    */
+typedef enum { DM_NCOV_DIAG3 = 0 } dm_ncov;
+
+typedef struct {
+    int kind;      /* dm_grid_kind                                        */
+    int nside;     /* HEALPix resolution (kind 0)                         */
+    int ntheta;    /* Gauss-Legendre rings (kind 1)                       */
+    int nphi;      /* pixels per Gauss-Legendre ring (kind 1)             */
+} dm_grid;
+
+/* Cooling schedule (Algorithm 1, Sec. 3.2): xi_k = lambda_k * tau with
+ * lambda_k = lambda_start^(1 - k/(nsteps-1)), k = 0..nsteps-1 (the last
+ * step has lambda = 1, i.e. mu = 0), and iters_per_step iterations per
+ * step.  nsteps = 1 runs only lambda = 1.                                  */
+typedef struct {
+    double lambda_start;   /* >= 1                                          */
+    int nsteps;            /* >= 1                                          */
+    int iters_per_step;    /* >= 1                                          */
+} dm_schedule;
+
+/* Per right-hand side diagnostics.  residual = ||A x - y|| / ||y|| with
+ * A = 1 + S^1/2 Y^T N^-1 Y S^1/2, x = S^+1/2 u, y = S^1/2 Y^T N^-1 d
+ * (Appendix C); chi2 = (d - Y u)^T N^-1 (d - Y u) + u^T S^+ u (eq 3);
+ * cauchy = ||u_i - u_{i-1}|| / ||u_i|| at the last iteration (Algorithm 1's
+ * stopping ratio); seconds = wall time of the whole call.               */
+typedef struct {
+    int iterations;
+    double residual;
+    double cauchy;
+    double chi2;
+    double seconds;
+} dm_stats;
+
+typedef struct dm_plan dm_plan;   /* opaque; owns all device memory */
+
+/* ABI version of the loaded library (DMWF_ABI_VERSION).                   */
+int dm_abi_version(void);
+
+/* Number of visible HIP devices (0 when there is none).                   */
+int dm_device_count(void);
+
+/* Create a plan for a grid, band limit lmax (>= 2, and <= 3 nside - 1 on
+ * HEALPix, <= ntheta - 1 and <= (nphi - 1) / 2 on Gauss-Legendre), up to
+ * max_rhs right-hand sides per call, on HIP device `device`.  Builds ring
+ * tables, recursion coefficients and the per-(m, ring) recursion seeds.
+ * Returns DM_EDEVICE without a GPU, DM_EINVAL on bad sizes,
+ * DM_EUNSUPPORTED for a ring length that this build's FFT cannot stage.  */
+dm_status dm_plan_create(dm_plan** plan, const dm_grid* grid, int lmax, int max_rhs,
+                         dm_precision precision, int device);
+dm_status dm_plan_destroy(dm_plan* plan);
+
+/* Grid facts of a plan: npix, nalm, number of rings.                       */
+dm_status dm_plan_info(const dm_plan* plan, int64_t* npix, int64_t* nalm, int* nrings);
+
+/* Signal covariance (eq 10): cl [4][lmax+1] in the order TT, EE, BB, TE.
+ * Each S_l must be positive semi-definite (TE^2 <= TT EE, all >= 0) and
+ * finite; E and B entries below l = 2 are ignored.                        */
+dm_status dm_set_spectra(dm_plan* plan, const double* cl);
+
+/* Noise covariance (eq 11, diagonal) and mask: ncov [3][npix] variances,
+ * obs [npix] with 1 = observed, 0 = masked (NULL = all observed).
+ * Observed variances must be finite and > 0; masked pixels get N^-1 = 0
+ * (Appendix B).  Sets tau = min over observed pixels of (min variance x
+ * pixel weight), the messenger covariance of eq 4.                       */
+dm_status dm_set_noise(dm_plan* plan, const double* ncov, dm_ncov layout, const uint8_t* obs);
+
+/* Cooling schedule; the default is {1e3, 20, 10}.                          */
+dm_status dm_set_schedule(dm_plan* plan, const dm_schedule* schedule);
+
+/* Wiener filter of nrhs data maps d [nrhs][3][npix] (Algorithm 1).  Writes
+ * the final iterate u (the Wiener-filtered T, E, B alm) to alm
+ * [nrhs][3][nalm][2], optionally the map Y u to map [nrhs][3][npix]
+ * (nullable), and optionally diagnostics to stats[nrhs] (nullable; the
+ * residual and chi2 cost two extra adjoint transforms).  Masked pixels of
+ * d are ignored.  DM_ENONFINITE if the iterate became non-finite.        */
+dm_status dm_wiener_filter(dm_plan* plan, int nrhs, const double* d, double* alm, double* map,
+                           dm_stats* stats);
+
+/* Same on device buffers (double): d, alm, map (nullable) are device
+ * pointers; work is enqueued on hip_stream.  stats (host, nullable) forces
+ * a synchronisation at the end.                                          */
+dm_status dm_wiener_filter_device(dm_plan* plan, int nrhs, const void* d, void* alm, void* map,
+                                  void* hip_stream, dm_stats* stats);
+
+/* Constrained realizations, eq 19: s_CR,k = W(d - d_hat_k) + s_hat_k for
+ * k < nreal, run as one batch of nreal + 1 right-hand sides (the extra one
+ * is W d).  d [3][npix]; shat_alm [nreal][3][nalm][2]; dhat
+ * [nreal][3][npix] (fake data Y s_hat + n_hat made by the caller);
+ * scr_alm [nreal][3][nalm][2]; f_alm (nullable) receives the fluctuation
+ * parts f_k = s_CR,k - W d.  Needs max_rhs >= nreal + 1.                 */
+dm_status dm_constrained_realizations(dm_plan* plan, int nreal, const double* d,
+                                      const double* shat_alm, const double* dhat,
+                                      double* scr_alm, double* f_alm);
+
+/* Single transforms (host buffers), nrhs at a time.                       */
+dm_status dm_alm2map(dm_plan* plan, int nrhs, const double* alm, double* map);          /* Y     */
+dm_status dm_map2alm(dm_plan* plan, int nrhs, const double* map, double* alm);          /* Y^T W */
+dm_status dm_alm2map_adjoint(dm_plan* plan, int nrhs, const double* map, double* alm);  /* Y^T   */
+
+/* Single transforms on device buffers (double), enqueued on hip_stream.   */
+dm_status dm_alm2map_device(dm_plan* plan, int nrhs, const void* alm, void* map, void* hip_stream);
+dm_status dm_map2alm_device(dm_plan* plan, int nrhs, const void* map, void* alm, void* hip_stream);
+
+/* Run `niter` messenger iterations at a fixed lambda (mu = (lambda-1) tau)
+ * from a given messenger map t_in [nrhs][3][npix] (no masking applied to
+ * it), with the data d [nrhs][3][npix] of the current noise setup:
+ *   t_hat = A t, u = F^mu t_hat, u_x = Y u, t = K u_x + b.
+ * Writes the last u to alm and the last t to t_out (nullable).  Used to
+ * check single iterations step by step.                                  */
+dm_status dm_iterate(dm_plan* plan, int nrhs, const double* d, const double* t_in, double lambda,
+                     int niter, double* alm, double* t_out);
+
+/* Per-kernel GPU timing, measured with HIP events on the plan's stream
+ * when enabled: enable != 0 turns recording on and clears the totals.
+ * dm_kernel_times writes, for kernel class k < *count (0 Legendre
+ * analysis, 1 Legendre synthesis, 2 ring FFT + pointwise, 3 combine and
+ * filter), the total milliseconds to ms[k] and the number of launches to
+ * launches[k].                                                            */
+dm_status dm_profile_enable(dm_plan* plan, int enable);
+dm_status dm_kernel_times(dm_plan* plan, double* ms, int64_t* launches, int* count);
+
+/* Text of the last error on this plan (or of the last failed
+ * dm_plan_create when plan is NULL).  Valid until the next call.          */
+const char* dm_last_error(const dm_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMWF_H */

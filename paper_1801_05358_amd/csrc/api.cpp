@@ -1,0 +1,781 @@
+// C ABI of libdmwf (include/dmwf.h): plan lifecycle, input validation, the
+// dual messenger solve (Algorithm 1) orchestrated as a sequence of HIP
+// kernels on one stream, the diagnostics, and constrained realizations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dmwf_internal.h"
+
+using namespace dmwf;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct Fail {
+    dm_status st;
+};
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            p->err = std::string(#expr) + ": " + hipGetErrorString(e_);                           \
+            throw Fail{e_ == hipErrorOutOfMemory ? DM_ENOMEM : DM_EDEVICE};                       \
+        }                                                                                         \
+    } while (0)
+
+#define REQUIRE(cond, code, msg)         \
+    do {                                 \
+        if (!(cond)) {                   \
+            p->err = (msg);              \
+            throw Fail{code};            \
+        }                                \
+    } while (0)
+
+template <class T>
+void dalloc(dm_plan* p, T*& ptr, size_t count) {
+    if (ptr) {
+        (void)hipFree(ptr);
+        ptr = nullptr;
+    }
+    if (count == 0) count = 1;
+    HIPCHK(hipMalloc((void**)&ptr, count * sizeof(T)));
+}
+
+template <class T>
+void dfree(T*& ptr) {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+}
+
+template <class T>
+void upload(dm_plan* p, T* dst, const T* src, size_t count) {
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, p->stream));
+}
+
+bool all_finite(const double* x, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// timing of kernel classes with HIP events
+// --------------------------------------------------------------------------
+struct Timed {
+    dm_plan* p;
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(dm_plan* p_, int c, hipStream_t s_) : p(p_), cls(c), s(s_) {
+        if (p->profiling) {
+            HIPCHK(hipEventCreate(&a));
+            HIPCHK(hipEventCreate(&b));
+            HIPCHK(hipEventRecord(a, s));
+        }
+    }
+    void done() {
+        if (p->profiling) {
+            HIPCHK(hipEventRecord(b, s));
+            p->ev.start.push_back(a);
+            p->ev.stop.push_back(b);
+            p->ev.cls.push_back(cls);
+        }
+    }
+};
+
+void collect_events(dm_plan* p) {
+    for (size_t i = 0; i < p->ev.start.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev.start[i], p->ev.stop[i]) == hipSuccess) {
+            p->kc_ms[p->ev.cls[i]] += ms;
+            p->kc_n[p->ev.cls[i]] += 1;
+        }
+        (void)hipEventDestroy(p->ev.start[i]);
+        (void)hipEventDestroy(p->ev.stop[i]);
+    }
+    p->ev.start.clear();
+    p->ev.stop.clear();
+    p->ev.cls.clear();
+}
+
+// --------------------------------------------------------------------------
+// transform building blocks
+// --------------------------------------------------------------------------
+void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const double* b, double* phase,
+          hipStream_t s) {
+    Timed t(p, KC_RING, s);
+    HIPCHK(launch_ring(p, mode, nrhs, in, out, p->d_K, b, phase, s));
+    t.done();
+}
+
+// analysis + combine: alm = filter(A t) in (T, E, B); spin (nullable)
+// receives the same coefficients in the spin basis for the synthesis
+void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, const double* filter, double* alm,
+                  double* spin, hipStream_t s) {
+    {
+        Timed t(p, KC_LEG_ANALYSIS, s);
+        HIPCHK(launch_leg_analysis(p, nrhs, phase, weighted ? p->d_pair_w : p->d_pair_one, p->d_partial, s));
+        t.done();
+    }
+    Timed t(p, KC_COMBINE, s);
+    HIPCHK(launch_combine(p, nrhs, p->d_partial, filter, alm, spin, s));
+    t.done();
+}
+
+// synthesis from spin-basis coefficients
+void leg_synthesis(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
+    Timed t(p, KC_LEG_SYNTHESIS, s);
+    HIPCHK(launch_leg_synthesis(p, nrhs, spin, phase, s));
+    t.done();
+}
+
+// map (device) -> alm (device): A = Y^T W (weighted) or Y^T
+void map2alm_dev(dm_plan* p, int nrhs, const double* map, double* alm, bool weighted, hipStream_t s) {
+    ring(p, RING_ANALYSIS, nrhs, map, nullptr, nullptr, p->d_phase, s);
+    leg_analysis(p, nrhs, p->d_phase, weighted, nullptr, alm, nullptr, s);
+}
+
+void alm2map_dev(dm_plan* p, int nrhs, const double* alm, double* map, hipStream_t s) {
+    HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, s));
+    leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
+    ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, p->d_phase, s);
+}
+
+void check_rhs(dm_plan* p, int nrhs) {
+    REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, DM_EINVAL,
+            "nrhs must be in [1, max_rhs=" + std::to_string(p->max_rhs) + "]");
+}
+
+// upload all cooling-step filters [nsteps][lmax+1][4] for the schedule
+void prepare_filters(dm_plan* p, const std::vector<double>& lambdas) {
+    const size_t per = (size_t)(p->lmax + 1) * 4;
+    const size_t need = per * lambdas.size();
+    if ((int)lambdas.size() > p->filters_cap) {
+        dalloc(p, p->d_filters, need);
+        p->filters_cap = (int)lambdas.size();
+    }
+    if (p->h_pinned_len < need) {
+        HIPCHK(hipStreamSynchronize(p->stream));
+        if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+        p->h_pinned = nullptr;
+        HIPCHK(hipHostMalloc((void**)&p->h_pinned, need * sizeof(double), hipHostMallocDefault));
+        p->h_pinned_len = need;
+    }
+    std::vector<double> F;
+    for (size_t k = 0; k < lambdas.size(); ++k) {
+        build_filter(p->cl, p->lmax, (lambdas[k] - 1.0) * p->tau, p->tau, F);
+        std::memcpy(p->h_pinned + k * per, F.data(), per * sizeof(double));
+    }
+    HIPCHK(hipMemcpyAsync(p->d_filters, p->h_pinned, need * sizeof(double), hipMemcpyHostToDevice, p->stream));
+}
+
+std::vector<double> schedule_lambdas(const dm_schedule& sc) {
+    std::vector<double> lam(sc.nsteps, 1.0);
+    if (sc.nsteps > 1)
+        for (int k = 0; k < sc.nsteps - 1; ++k)
+            lam[k] = std::pow(sc.lambda_start, 1.0 - (double)k / (sc.nsteps - 1));
+    return lam;
+}
+
+void sync_plan_stream_to(dm_plan* p, hipStream_t s) {
+    if (s == p->stream) return;
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(e, p->stream));
+    HIPCHK(hipStreamWaitEvent(s, e, 0));
+    HIPCHK(hipEventDestroy(e));
+}
+
+// The dual messenger solve on device buffers (Algorithm 1).
+//   d: [nrhs][3][npix] device; alm: [nrhs][3][nalm] complex device;
+//   map: nullable device [nrhs][3][npix] (receives Y u).
+void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, hipStream_t s, dm_stats* stats) {
+    REQUIRE(p->noise_set, DM_ESTATE, "dm_set_noise must be called before solving");
+    REQUIRE(p->spectra_set, DM_ESTATE, "dm_set_spectra must be called before solving");
+    check_rhs(p, nrhs);
+    const auto t0 = std::chrono::steady_clock::now();
+    const std::vector<double> lam = schedule_lambdas(p->sched);
+    prepare_filters(p, lam);
+    sync_plan_stream_to(p, s);
+    const size_t per = (size_t)(p->lmax + 1) * 4;
+    const int64_t alm_len = (int64_t)nrhs * 3 * p->nalm * 2;
+
+    // setup: d0 = mask(d), b = T N^-1 d0, t_0 = d0
+    HIPCHK(launch_data_setup(p, nrhs, d, p->d_d0, p->d_b, s));
+    ring(p, RING_ANALYSIS, nrhs, p->d_d0, nullptr, nullptr, p->d_phase, s);
+    const int nsteps = (int)lam.size(), niter = p->sched.iters_per_step;
+    const int total = nsteps * niter;
+    int it = 0;
+    for (int k = 0; k < nsteps; ++k) {
+        const double* F = p->d_filters + per * k;
+        for (int i = 0; i < niter; ++i, ++it) {
+            const bool last = (it == total - 1);
+            if (last && stats) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_len * sizeof(double),
+                                                     hipMemcpyDeviceToDevice, s));
+            // t_hat = A t ; u = F t_hat        (eq 8)
+            leg_analysis(p, nrhs, p->d_phase, true, F, alm, p->d_alm_spin, s);
+            // u_x = Y u                          (synthesis)
+            leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
+            if (!last) {
+                // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
+                ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, p->d_phase, s);
+            } else {
+                ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
+            }
+        }
+    }
+    if (map) HIPCHK(hipMemcpyAsync(map, p->d_ux, (size_t)nrhs * 3 * p->npix * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s));
+    // non-finite check of the iterate
+    int* d_cnt = reinterpret_cast<int*>(p->d_red);
+    HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(int), s));
+    HIPCHK(launch_count_nonfinite(alm, alm_len, d_cnt, s));
+    int cnt = 0;
+    if (stats) {
+        // residual maps, their adjoints, and the norms
+        double* chi = p->d_red + 64;
+        HIPCHK(launch_residual_maps(p, nrhs, p->d_ux, p->d_d0, p->d_b, chi, s));
+        map2alm_dev(p, nrhs, p->d_ux, p->d_alm_r, false, s);
+        map2alm_dev(p, nrhs, p->d_b, p->d_alm_y, false, s);
+        const int nb = alm_norm_blocks(p);
+        double* parts = chi + (int64_t)nrhs * p->nrings;
+        HIPCHK(launch_alm_norms(p, nrhs, alm, p->d_alm_prev, p->d_alm_r, p->d_alm_y, p->d_mats, parts, s));
+        std::vector<double> hchi((size_t)nrhs * p->nrings), hparts((size_t)nrhs * nb * kNormQ);
+        HIPCHK(hipMemcpyAsync(hchi.data(), chi, hchi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hparts.data(), parts, hparts.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&cnt, d_cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int r = 0; r < nrhs; ++r) {
+            double q[kNormQ] = {0, 0, 0, 0, 0};
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < kNormQ; ++k) q[k] += hparts[((size_t)r * nb + b) * kNormQ + k];
+            double c = 0;
+            for (int j = 0; j < p->nrings; ++j) c += hchi[(size_t)r * p->nrings + j];
+            stats[r].iterations = total;
+            stats[r].cauchy = q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0;
+            stats[r].residual = q[3] > 0 ? std::sqrt(q[2] / q[3]) : 0.0;
+            stats[r].chi2 = c + q[4];
+            stats[r].seconds = secs;
+        }
+    } else {
+        HIPCHK(hipMemcpyAsync(&cnt, d_cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    if (p->profiling) collect_events(p);
+    REQUIRE(cnt == 0, DM_ENONFINITE, "the iterate became non-finite");
+}
+
+void free_plan(dm_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    for (size_t i = 0; i < p->ev.start.size(); ++i) {
+        (void)hipEventDestroy(p->ev.start[i]);
+        (void)hipEventDestroy(p->ev.stop[i]);
+    }
+    dfree(p->d_pair_x); dfree(p->d_pair_w); dfree(p->d_pair_one); dfree(p->d_pairs); dfree(p->d_fftlen);
+    dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
+    dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
+    dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_partial);
+    dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
+    dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
+    if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+template <class F>
+dm_status guarded(dm_plan* p, F&& f) {
+    if (!p) return DM_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(p->device));
+        p->err.clear();
+        f();
+        return DM_OK;
+    } catch (const Fail& e) {
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        p->err = "host allocation failed";
+        return DM_ENOMEM;
+    } catch (...) {
+        p->err = "internal error";
+        return DM_EDEVICE;
+    }
+}
+
+}  // namespace
+
+// ==========================================================================
+// ABI
+// ==========================================================================
+extern "C" {
+
+int dm_abi_version(void) { return DMWF_ABI_VERSION; }
+
+int dm_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+const char* dm_last_error(const dm_plan* p) { return p ? p->err.c_str() : g_create_err.c_str(); }
+
+dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_rhs, dm_precision precision,
+                         int device) {
+    g_create_err.clear();
+    if (!out || !grid) {
+        g_create_err = "null argument";
+        return DM_EINVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        g_create_err = "no HIP device available";
+        return DM_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_err = "device index out of range";
+        return DM_EINVAL;
+    }
+    dm_plan* p = new (std::nothrow) dm_plan();
+    if (!p) {
+        g_create_err = "host allocation failed";
+        return DM_ENOMEM;
+    }
+    p->device = device;
+    p->grid = *grid;
+    p->lmax = lmax;
+    p->mmax = lmax;
+    p->max_rhs = max_rhs;
+    p->precision = precision;
+    try {
+        HIPCHK(hipSetDevice(device));
+        REQUIRE(precision == DM_FP64 || precision == DM_MIXED, DM_EINVAL, "unknown precision");
+        REQUIRE(precision == DM_FP64, DM_EUNSUPPORTED, "this build implements DM_FP64 only");
+        REQUIRE(max_rhs >= 1 && max_rhs <= 4096, DM_EINVAL, "max_rhs must be in [1, 4096]");
+        REQUIRE(lmax >= 2 && lmax <= 16384, DM_EINVAL, "lmax must be in [2, 16384]");
+        std::string e;
+        REQUIRE(build_rings(*grid, p->rings, p->npix, e), DM_EINVAL, e);
+        if (grid->kind == DM_GRID_HEALPIX_RING)
+            REQUIRE(lmax <= 3 * grid->nside - 1, DM_EINVAL, "lmax must be <= 3 nside - 1 on HEALPix");
+        else
+            REQUIRE(lmax <= grid->ntheta - 1 && 2 * lmax + 1 <= grid->nphi, DM_EINVAL,
+                    "Gauss-Legendre needs ntheta >= lmax + 1 and nphi >= 2 lmax + 1");
+        p->nrings = (int)p->rings.z.size();
+        p->npairs = (int)p->rings.pair_n.size();
+        p->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
+        REQUIRE(build_fft_tables(p->rings, p->mmax, p->fft, e), DM_EINVAL, e);
+        p->fft_lds_bytes = (size_t)p->fft.Mmax * 16;
+        REQUIRE(p->fft_lds_bytes <= 160 * 1024, DM_EUNSUPPORTED,
+                "ring length needs an FFT of " + std::to_string(p->fft.Mmax) +
+                    " points, beyond the LDS of one workgroup in double precision");
+        HIPCHK(hipStreamCreate(&p->stream));
+
+        // ring and pair tables
+        std::vector<double> px(p->npairs), pw(p->npairs), one(p->npairs, 1.0);
+        std::vector<RingPairDev> pd(p->npairs);
+        for (int q = 0; q < p->npairs; ++q) {
+            const int rn = p->rings.pair_n[q], rs = p->rings.pair_s[q];
+            px[q] = p->rings.z[rn];
+            pw[q] = p->rings.w[rn];
+            RingPairDev& d = pd[q];
+            d.nphi = p->rings.nphi[rn];
+            d.len_idx = (int)(std::lower_bound(p->fft.n.begin(), p->fft.n.end(), d.nphi) - p->fft.n.begin());
+            d.has_s = rs >= 0;
+            d.off_n = p->rings.offset[rn];
+            d.off_s = rs >= 0 ? p->rings.offset[rs] : 0;
+            // phi0 = pi / den for HEALPix (den = 4i or 4 nside), 0 otherwise
+            d.phi0_den = 0;
+            const double ph = p->rings.phi0[rn];
+            if (ph > 0) d.phi0_den = (int)std::lround(M_PI / ph);
+        }
+        std::vector<FftLenDev> fl(p->fft.n.size());
+        for (size_t i = 0; i < fl.size(); ++i) {
+            fl[i].n = p->fft.n[i];
+            fl[i].M = p->fft.M[i];
+            fl[i].logM = p->fft.logM[i];
+            fl[i].bluestein = p->fft.chirp_off[i] >= 0;
+            fl[i].chirp_off = std::max<int64_t>(p->fft.chirp_off[i], 0);
+            fl[i].bhat_off = std::max<int64_t>(p->fft.bhat_off[i], 0);
+        }
+        dalloc(p, p->d_pair_x, p->npairs);
+        dalloc(p, p->d_pair_w, p->npairs);
+        dalloc(p, p->d_pair_one, p->npairs);
+        dalloc(p, p->d_pairs, p->npairs);
+        dalloc(p, p->d_fftlen, fl.size());
+        dalloc(p, p->d_chirp, p->fft.chirp.size());
+        dalloc(p, p->d_bhat, p->fft.bhat.size());
+        dalloc(p, p->d_tw, p->fft.tw.size());
+        upload(p, p->d_pair_x, px.data(), px.size());
+        upload(p, p->d_pair_w, pw.data(), pw.size());
+        upload(p, p->d_pair_one, one.data(), one.size());
+        upload(p, p->d_pairs, pd.data(), pd.size());
+        upload(p, p->d_fftlen, fl.data(), fl.size());
+        if (!p->fft.chirp.empty()) upload(p, p->d_chirp, p->fft.chirp.data(), p->fft.chirp.size());
+        if (!p->fft.bhat.empty()) upload(p, p->d_bhat, p->fft.bhat.data(), p->fft.bhat.size());
+        upload(p, p->d_tw, p->fft.tw.data(), p->fft.tw.size());
+        HIPCHK(ring_set_lds_limit(p->fft_lds_bytes));
+        std::vector<int64_t> roff(p->rings.offset.begin(), p->rings.offset.end());
+        dalloc(p, p->d_ring_w, p->nrings);
+        dalloc(p, p->d_ring_off, p->nrings);
+        dalloc(p, p->d_ring_n, p->nrings);
+        upload(p, p->d_ring_w, p->rings.w.data(), p->nrings);
+        upload(p, p->d_ring_off, roff.data(), p->nrings);
+        upload(p, p->d_ring_n, p->rings.nphi.data(), p->nrings);
+
+        // recursion coefficients and seeds
+        std::vector<double> coef, lp0, lp2;
+        build_coefficients(lmax, coef, lp0, lp2);
+        dalloc(p, p->d_coef, coef.size());
+        dalloc(p, p->d_lp0, lp0.size());
+        dalloc(p, p->d_lp2, lp2.size());
+        upload(p, p->d_coef, coef.data(), coef.size());
+        upload(p, p->d_lp0, lp0.data(), lp0.size());
+        upload(p, p->d_lp2, lp2.data(), lp2.size());
+        const size_t sn = (size_t)(p->mmax + 1) * p->npairs;
+        dalloc(p, p->d_lstart, sn);
+        dalloc(p, p->d_seed, sn * kSeedFields);
+        HIPCHK(launch_seeds(p, p->stream));
+
+        // analysis tiling: ring pairs per workgroup = 256 threads x R
+        p->ana_R = p->npairs >= 1024 ? 4 : (p->npairs >= 512 ? 2 : 1);
+        p->ana_chunks = (p->npairs + 256 * p->ana_R - 1) / (256 * p->ana_R);
+        p->syn_threads = 128;
+        p->syn_R = 1;
+
+        // work buffers
+        const size_t B = (size_t)max_rhs;
+        dalloc(p, p->d_phase, B * 3 * p->npairs * (p->mmax + 1) * 4);
+        dalloc(p, p->d_partial, (size_t)p->ana_chunks * B * 3 * p->nalm * 2);
+        dalloc(p, p->d_alm, B * 3 * p->nalm * 2);
+        dalloc(p, p->d_alm_prev, B * 3 * p->nalm * 2);
+        dalloc(p, p->d_alm_spin, B * 3 * p->nalm * 2);
+        dalloc(p, p->d_alm_r, B * 3 * p->nalm * 2);
+        dalloc(p, p->d_alm_y, B * 3 * p->nalm * 2);
+        dalloc(p, p->d_d0, B * 3 * p->npix);
+        dalloc(p, p->d_b, B * 3 * p->npix);
+        dalloc(p, p->d_ux, B * 3 * p->npix);
+        dalloc(p, p->d_K, 3 * p->npix);
+        dalloc(p, p->d_tn, 3 * p->npix);
+        dalloc(p, p->d_ninv, 3 * p->npix);
+        dalloc(p, p->d_obs, p->npix);
+        dalloc(p, p->d_mats, 3 * (size_t)(lmax + 1) * 4);
+        p->red_len = 64 + B * p->nrings + B * (size_t)alm_norm_blocks(p) * kNormQ + p->nrings;
+        dalloc(p, p->d_red, p->red_len);
+        HIPCHK(hipStreamSynchronize(p->stream));
+        p->cl.assign(4 * (size_t)(lmax + 1), 0.0);
+    } catch (const Fail& f) {
+        g_create_err = p->err;
+        free_plan(p);
+        return f.st;
+    } catch (...) {
+        g_create_err = "internal error during plan creation";
+        free_plan(p);
+        return DM_EDEVICE;
+    }
+    *out = p;
+    return DM_OK;
+}
+
+dm_status dm_plan_destroy(dm_plan* p) {
+    if (!p) return DM_EINVAL;
+    free_plan(p);
+    return DM_OK;
+}
+
+dm_status dm_plan_info(const dm_plan* p, int64_t* npix, int64_t* nalm, int* nrings) {
+    if (!p) return DM_EINVAL;
+    if (npix) *npix = p->npix;
+    if (nalm) *nalm = p->nalm;
+    if (nrings) *nrings = p->nrings;
+    return DM_OK;
+}
+
+dm_status dm_set_spectra(dm_plan* p, const double* cl) {
+    return guarded(p, [&] {
+        REQUIRE(cl != nullptr, DM_EINVAL, "cl is null");
+        const int L = p->lmax + 1;
+        REQUIRE(all_finite(cl, 4 * (size_t)L), DM_EINVAL, "spectra must be finite");
+        std::vector<double> c(cl, cl + 4 * (size_t)L);
+        for (int l = 0; l < L; ++l) {
+            if (l < 2) {
+                c[1 * L + l] = c[2 * L + l] = c[3 * L + l] = 0.0;   // no E, B below l = 2
+            }
+            const double TT = c[l], EE = c[L + l], BB = c[2 * L + l], TE = c[3 * L + l];
+            REQUIRE(TT >= 0 && EE >= 0 && BB >= 0 && TE * TE <= TT * EE * (1 + 1e-12), DM_EINVAL,
+                    "S_l must be positive semi-definite at l = " + std::to_string(l));
+        }
+        p->cl = c;
+        std::vector<double> m1, m2, m3, all;
+        build_matrix_function(p->cl, p->lmax, 1, m1);
+        build_matrix_function(p->cl, p->lmax, 2, m2);
+        build_matrix_function(p->cl, p->lmax, 3, m3);
+        all.insert(all.end(), m1.begin(), m1.end());
+        all.insert(all.end(), m2.begin(), m2.end());
+        all.insert(all.end(), m3.begin(), m3.end());
+        upload(p, p->d_mats, all.data(), all.size());
+        HIPCHK(hipStreamSynchronize(p->stream));
+        p->spectra_set = true;
+    });
+}
+
+dm_status dm_set_noise(dm_plan* p, const double* ncov, dm_ncov layout, const uint8_t* obs) {
+    return guarded(p, [&] {
+        REQUIRE(ncov != nullptr, DM_EINVAL, "ncov is null");
+        REQUIRE(layout == DM_NCOV_DIAG3, DM_EUNSUPPORTED, "only DM_NCOV_DIAG3 noise is implemented");
+        const int64_t n = p->npix;
+        int64_t nobs = 0;
+        for (int64_t q = 0; q < n; ++q) {
+            if (obs && !obs[q]) continue;
+            ++nobs;
+            for (int f = 0; f < 3; ++f) {
+                const double v = ncov[f * n + q];
+                REQUIRE(std::isfinite(v) && v > 0, DM_EINVAL,
+                        "observed noise variances must be finite and > 0 (pixel " + std::to_string(q) + ")");
+            }
+        }
+        REQUIRE(nobs > 0, DM_EINVAL, "every pixel is masked");
+        p->noise_set = false;
+        double* d_ncov = nullptr;
+        HIPCHK(hipMalloc((void**)&d_ncov, 3 * n * sizeof(double)));
+        std::unique_ptr<double, void (*)(double*)> guard(d_ncov, [](double* x) { (void)hipFree(x); });
+        upload(p, d_ncov, ncov, 3 * n);
+        uint8_t* dobs = nullptr;
+        if (obs) {
+            upload(p, p->d_obs, obs, n);
+            dobs = p->d_obs;
+        } else {
+            HIPCHK(hipMemsetAsync(p->d_obs, 1, n, p->stream));
+        }
+        double* ring_min = p->d_red + 64;
+        HIPCHK(launch_tau_parts(p, d_ncov, dobs, ring_min, p->stream));
+        std::vector<double> rm(p->nrings);
+        HIPCHK(hipMemcpyAsync(rm.data(), ring_min, rm.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        double tau = INFINITY;
+        for (double v : rm) tau = std::min(tau, v);
+        REQUIRE(std::isfinite(tau) && tau > 0, DM_EINVAL, "no valid observed pixel");
+        p->tau = tau;
+        HIPCHK(launch_noise_setup(p, d_ncov, dobs, tau, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        p->noise_set = true;
+    });
+}
+
+dm_status dm_set_schedule(dm_plan* p, const dm_schedule* sc) {
+    return guarded(p, [&] {
+        REQUIRE(sc != nullptr, DM_EINVAL, "schedule is null");
+        REQUIRE(std::isfinite(sc->lambda_start) && sc->lambda_start >= 1.0, DM_EINVAL, "lambda_start must be >= 1");
+        REQUIRE(sc->nsteps >= 1 && sc->nsteps <= 100000, DM_EINVAL, "nsteps must be in [1, 100000]");
+        REQUIRE(sc->iters_per_step >= 1 && sc->iters_per_step <= 10000000, DM_EINVAL, "iters_per_step must be >= 1");
+        p->sched = *sc;
+    });
+}
+
+dm_status dm_wiener_filter(dm_plan* p, int nrhs, const double* d, double* alm, double* map, dm_stats* stats) {
+    return guarded(p, [&] {
+        REQUIRE(d && alm, DM_EINVAL, "d and alm must not be null");
+        check_rhs(p, nrhs);
+        const size_t nmap = (size_t)nrhs * 3 * p->npix;
+        REQUIRE(all_finite(d, nmap), DM_EINVAL, "d must be finite");
+        double *dd = nullptr, *da = nullptr, *dm = nullptr;
+        auto del = [](double* x) { if (x) (void)hipFree(x); };
+        HIPCHK(hipMalloc((void**)&dd, nmap * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g1(dd, del);
+        HIPCHK(hipMalloc((void**)&da, (size_t)nrhs * 3 * p->nalm * 2 * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g2(da, del);
+        if (map) HIPCHK(hipMalloc((void**)&dm, nmap * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g3(dm, del);
+        upload(p, dd, d, nmap);
+        solve_dev(p, nrhs, dd, da, dm, p->stream, stats);
+        HIPCHK(hipMemcpyAsync(alm, da, (size_t)nrhs * 3 * p->nalm * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+        if (map) HIPCHK(hipMemcpyAsync(map, dm, nmap * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+    });
+}
+
+dm_status dm_wiener_filter_device(dm_plan* p, int nrhs, const void* d, void* alm, void* map, void* hip_stream,
+                                  dm_stats* stats) {
+    return guarded(p, [&] {
+        REQUIRE(d && alm, DM_EINVAL, "d and alm must not be null");
+        check_rhs(p, nrhs);
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        // the data must be finite (checked on the device)
+        int* d_cnt = reinterpret_cast<int*>(p->d_red);
+        sync_plan_stream_to(p, s);
+        HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(int), s));
+        HIPCHK(launch_count_nonfinite((const double*)d, (int64_t)nrhs * 3 * p->npix, d_cnt, s));
+        int cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, d_cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        REQUIRE(cnt == 0, DM_EINVAL, "d must be finite");
+        solve_dev(p, nrhs, (const double*)d, (double*)alm, (double*)map, s, stats);
+    });
+}
+
+dm_status dm_constrained_realizations(dm_plan* p, int nreal, const double* d, const double* shat_alm,
+                                      const double* dhat, double* scr_alm, double* f_alm) {
+    return guarded(p, [&] {
+        REQUIRE(d && shat_alm && dhat && scr_alm, DM_EINVAL, "null argument");
+        REQUIRE(nreal >= 1, DM_EINVAL, "nreal must be >= 1");
+        const int B = nreal + 1;
+        check_rhs(p, B);
+        const size_t nm = (size_t)3 * p->npix, na = (size_t)3 * p->nalm * 2;
+        REQUIRE(all_finite(d, nm) && all_finite(dhat, nm * nreal) && all_finite(shat_alm, na * nreal), DM_EINVAL,
+                "inputs must be finite");
+        double *dd = nullptr, *da = nullptr, *ds = nullptr;
+        auto del = [](double* x) { if (x) (void)hipFree(x); };
+        HIPCHK(hipMalloc((void**)&dd, nm * B * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g1(dd, del);
+        HIPCHK(hipMalloc((void**)&da, na * B * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g2(da, del);
+        HIPCHK(hipMalloc((void**)&ds, na * nreal * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g3(ds, del);
+        // right-hand sides: d, then d - d_hat_k   (eq 19)
+        upload(p, dd, d, nm);
+        upload(p, dd + nm, dhat, nm * nreal);
+        for (int k = 0; k < nreal; ++k)
+            HIPCHK(launch_axpby(dd + nm * (k + 1), dd, 1.0, -1.0, (int64_t)nm, p->stream));
+        upload(p, ds, shat_alm, na * nreal);
+        solve_dev(p, B, dd, da, nullptr, p->stream, nullptr);
+        // s_CR,k = W(d - d_hat_k) + s_hat_k
+        HIPCHK(launch_axpby(da + na, ds, 1.0, 1.0, (int64_t)(na * nreal), p->stream));
+        HIPCHK(hipMemcpyAsync(scr_alm, da + na, na * nreal * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        if (f_alm) {
+            // f_k = s_CR,k - W d
+            for (int k = 0; k < nreal; ++k)
+                HIPCHK(launch_axpby(da + na * (k + 1), da, -1.0, 1.0, (int64_t)na, p->stream));
+            HIPCHK(hipMemcpyAsync(f_alm, da + na, na * nreal * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        }
+        HIPCHK(hipStreamSynchronize(p->stream));
+    });
+}
+
+static dm_status transform_host(dm_plan* p, int nrhs, const double* in, double* out, int which) {
+    return guarded(p, [&] {
+        REQUIRE(in && out, DM_EINVAL, "null argument");
+        check_rhs(p, nrhs);
+        const size_t nm = (size_t)nrhs * 3 * p->npix, na = (size_t)nrhs * 3 * p->nalm * 2;
+        const size_t nin = which == 0 ? na : nm, nout = which == 0 ? nm : na;
+        REQUIRE(all_finite(in, nin), DM_EINVAL, "input must be finite");
+        double *di = nullptr, *dout = nullptr;
+        auto del = [](double* x) { if (x) (void)hipFree(x); };
+        HIPCHK(hipMalloc((void**)&di, nin * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g1(di, del);
+        HIPCHK(hipMalloc((void**)&dout, nout * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g2(dout, del);
+        upload(p, di, in, nin);
+        if (which == 0) alm2map_dev(p, nrhs, di, dout, p->stream);
+        else map2alm_dev(p, nrhs, di, dout, which == 1, p->stream);
+        HIPCHK(hipMemcpyAsync(out, dout, nout * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        if (p->profiling) collect_events(p);
+    });
+}
+
+dm_status dm_alm2map(dm_plan* p, int nrhs, const double* alm, double* map) { return transform_host(p, nrhs, alm, map, 0); }
+dm_status dm_map2alm(dm_plan* p, int nrhs, const double* map, double* alm) { return transform_host(p, nrhs, map, alm, 1); }
+dm_status dm_alm2map_adjoint(dm_plan* p, int nrhs, const double* map, double* alm) {
+    return transform_host(p, nrhs, map, alm, 2);
+}
+
+dm_status dm_alm2map_device(dm_plan* p, int nrhs, const void* alm, void* map, void* hip_stream) {
+    return guarded(p, [&] {
+        REQUIRE(alm && map, DM_EINVAL, "null argument");
+        check_rhs(p, nrhs);
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        sync_plan_stream_to(p, s);
+        alm2map_dev(p, nrhs, (const double*)alm, (double*)map, s);
+        if (p->profiling) {
+            HIPCHK(hipStreamSynchronize(s));
+            collect_events(p);
+        }
+    });
+}
+
+dm_status dm_map2alm_device(dm_plan* p, int nrhs, const void* map, void* alm, void* hip_stream) {
+    return guarded(p, [&] {
+        REQUIRE(alm && map, DM_EINVAL, "null argument");
+        check_rhs(p, nrhs);
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        sync_plan_stream_to(p, s);
+        map2alm_dev(p, nrhs, (const double*)map, (double*)alm, true, s);
+        if (p->profiling) {
+            HIPCHK(hipStreamSynchronize(s));
+            collect_events(p);
+        }
+    });
+}
+
+dm_status dm_iterate(dm_plan* p, int nrhs, const double* d, const double* t_in, double lambda, int niter, double* alm,
+                     double* t_out) {
+    return guarded(p, [&] {
+        REQUIRE(d && t_in && alm, DM_EINVAL, "null argument");
+        REQUIRE(p->noise_set && p->spectra_set, DM_ESTATE, "noise and spectra must be set");
+        REQUIRE(niter >= 1, DM_EINVAL, "niter must be >= 1");
+        REQUIRE(std::isfinite(lambda) && lambda >= 1.0, DM_EINVAL, "lambda must be >= 1");
+        check_rhs(p, nrhs);
+        const size_t nm = (size_t)nrhs * 3 * p->npix, na = (size_t)nrhs * 3 * p->nalm * 2;
+        REQUIRE(all_finite(d, nm) && all_finite(t_in, nm), DM_EINVAL, "inputs must be finite");
+        prepare_filters(p, std::vector<double>{lambda});
+        double *dd = nullptr, *dt = nullptr;
+        auto del = [](double* x) { if (x) (void)hipFree(x); };
+        HIPCHK(hipMalloc((void**)&dd, nm * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g1(dd, del);
+        HIPCHK(hipMalloc((void**)&dt, nm * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g2(dt, del);
+        upload(p, dd, d, nm);
+        upload(p, dt, t_in, nm);
+        HIPCHK(launch_data_setup(p, nrhs, dd, p->d_d0, p->d_b, p->stream));
+        ring(p, RING_ANALYSIS, nrhs, dt, nullptr, nullptr, p->d_phase, p->stream);
+        for (int i = 0; i < niter; ++i) {
+            leg_analysis(p, nrhs, p->d_phase, true, p->d_filters, p->d_alm, p->d_alm_spin, p->stream);
+            leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, p->stream);
+            ring(p, RING_ITERATE, nrhs, nullptr, (i == niter - 1) ? dt : nullptr, p->d_b, p->d_phase, p->stream);
+        }
+        HIPCHK(hipMemcpyAsync(alm, p->d_alm, na * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        if (t_out) HIPCHK(hipMemcpyAsync(t_out, dt, nm * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        if (p->profiling) collect_events(p);
+    });
+}
+
+dm_status dm_profile_enable(dm_plan* p, int enable) {
+    return guarded(p, [&] {
+        HIPCHK(hipStreamSynchronize(p->stream));
+        collect_events(p);
+        p->profiling = enable != 0;
+        for (int k = 0; k < KC_COUNT; ++k) {
+            p->kc_ms[k] = 0;
+            p->kc_n[k] = 0;
+        }
+    });
+}
+
+dm_status dm_kernel_times(dm_plan* p, double* ms, int64_t* launches, int* count) {
+    return guarded(p, [&] {
+        REQUIRE(ms && launches && count, DM_EINVAL, "null argument");
+        HIPCHK(hipDeviceSynchronize());
+        collect_events(p);
+        const int n = std::min(*count, (int)KC_COUNT);
+        for (int k = 0; k < n; ++k) {
+            ms[k] = p->kc_ms[k];
+            launches[k] = p->kc_n[k];
+        }
+        *count = KC_COUNT;
+    });
+}
+
+}  // extern "C"

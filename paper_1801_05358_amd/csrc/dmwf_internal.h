@@ -1,0 +1,199 @@
+// Internal declarations of libdmwf: the plan, its device tables and the
+// kernel launchers.  Not part of the public ABI (include/dmwf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmwf.h"
+
+namespace dmwf {
+
+// Recursion coefficients per packed (l, m), producing the value at l from
+// the values at l-1 and l-2 (see legendre.hip).
+constexpr int kCoefStride = 6;   // A0, B0, alpha, alpha*beta, gamma, pad
+
+// Per-(m, ring pair) recursion seeds: values at (ls-1, ls) of
+// lam, (+2)lam, (-2)lam (for m < 2 the spin-2 slots hold l = 1, 2).
+constexpr int kSeedFields = 6;
+
+// Kernel classes for the optional event timing.
+enum KernelClass { KC_LEG_ANALYSIS = 0, KC_LEG_SYNTHESIS = 1, KC_RING = 2, KC_COMBINE = 3, KC_COUNT = 4 };
+
+struct RingTables {
+    // per ring
+    std::vector<double> z;        // cos(theta)
+    std::vector<double> phi0;     // first pixel longitude
+    std::vector<double> w;        // per-pixel quadrature weight
+    std::vector<int> nphi;
+    std::vector<int64_t> offset;
+    // per ring pair (north ring p, south ring mirror or -1)
+    std::vector<int> pair_n, pair_s;
+};
+
+struct FftTables {
+    // distinct ring lengths
+    std::vector<int> n;           // length
+    std::vector<int> M;           // transform size (n if n is a power of two, else Bluestein size)
+    std::vector<int> logM;
+    std::vector<int64_t> chirp_off;   // offset into chirp (complex) or -1
+    std::vector<int64_t> bhat_off;    // offset into bhat (complex) or -1
+    int Mmax = 1;
+    std::vector<double> chirp;    // interleaved complex, exp(-i pi j^2 / n)
+    std::vector<double> bhat;     // interleaved complex, FFT_M(b) / M
+    std::vector<double> tw;       // interleaved complex, exp(-2 pi i k / Mmax), k < Mmax/2
+};
+
+// Device view of everything the ring (FFT) kernel needs per pair.
+struct RingPairDev {
+    int nphi;
+    int len_idx;      // index into the FFT length tables
+    int has_s;        // south ring present
+    int phi0_den;     // first-pixel longitude phi0 = pi / phi0_den (0: phi0 = 0)
+    int64_t off_n, off_s;
+};
+
+struct FftLenDev {
+    int n, M, logM, bluestein;
+    int64_t chirp_off, bhat_off;
+};
+
+struct GpuEvents {
+    std::vector<hipEvent_t> start, stop;
+    std::vector<int> cls;
+};
+
+}  // namespace dmwf
+
+struct dm_plan {
+    int device = 0;
+    hipStream_t stream = nullptr;       // plan-owned stream (default priority)
+    dm_grid grid{};
+    int lmax = 0, mmax = 0;
+    int64_t nalm = 0, npix = 0;
+    int nrings = 0, npairs = 0;
+    int max_rhs = 1;
+    dm_precision precision = DM_FP64;
+    std::string err;
+
+    dmwf::RingTables rings;
+    dmwf::FftTables fft;
+
+    // device tables
+    double* d_pair_x = nullptr;        // [npairs] cos theta of the north ring
+    double* d_pair_w = nullptr;        // [npairs] pixel weight
+    double* d_pair_one = nullptr;      // [npairs] ones (unweighted adjoint)
+    dmwf::RingPairDev* d_pairs = nullptr;
+    dmwf::FftLenDev* d_fftlen = nullptr;
+    double* d_chirp = nullptr;
+    double* d_bhat = nullptr;
+    double* d_tw = nullptr;
+    double* d_coef = nullptr;          // [nalm][kCoefStride]
+    int* d_lstart = nullptr;           // [mmax+1][npairs]
+    double* d_seed = nullptr;          // [kSeedFields][mmax+1][npairs]
+    double* d_lp0 = nullptr;           // [mmax+1] log seed prefactors, spin 0
+    double* d_lp2 = nullptr;           // [mmax+1] log seed prefactors, spin 2
+
+    // analysis tiling
+    int ana_threads = 256, ana_R = 2, ana_chunks = 1;
+    int syn_threads = 128, syn_R = 1;
+    int fft_threads = 512;
+    size_t fft_lds_bytes = 0;
+
+    // noise
+    bool noise_set = false;
+    double tau = 0.0;
+    double* d_K = nullptr;             // [3][npix]  1 - T N^-1
+    double* d_tn = nullptr;            // [3][npix]  T N^-1
+    double* d_ninv = nullptr;          // [3][npix]  N^-1 (0 in the mask)
+    uint8_t* d_obs = nullptr;          // [npix]
+    double* d_ring_w = nullptr;        // [nrings] pixel weight per ring
+    int64_t* d_ring_off = nullptr;     // [nrings]
+    int* d_ring_n = nullptr;           // [nrings]
+
+    // spectra / schedule
+    bool spectra_set = false;
+    std::vector<double> cl;            // [4][lmax+1]
+    dm_schedule sched{1e3, 20, 10};
+
+    // work buffers (sized for max_rhs)
+    double* d_phase = nullptr;         // [B][3][npairs][mmax+1][2] complex
+    double* d_partial = nullptr;       // [chunks][B][3][nalm] complex
+    double* d_alm = nullptr;           // [B][3][nalm] complex
+    double* d_alm_prev = nullptr;      // [B][3][nalm] complex
+    double* d_alm_spin = nullptr;      // [B][3][nalm] complex, (T, (2)a, (-2)a)
+    double* d_d0 = nullptr;            // [B][3][npix]  masked data
+    double* d_b = nullptr;             // [B][3][npix]  T N^-1 d
+    double* d_ux = nullptr;            // [B][3][npix]  Y u (scratch)
+    double* d_alm_r = nullptr;         // [B][3][nalm]  residual adjoint (scratch)
+    double* d_alm_y = nullptr;         // [B][3][nalm]
+    double* d_filters = nullptr;       // [nsteps][lmax+1][4]
+    int filters_cap = 0;
+    double* d_mats = nullptr;          // [3][lmax+1][4]  S^1/2, S^+1/2, S^+
+    double* h_pinned = nullptr;        // pinned staging for filters
+    size_t h_pinned_len = 0;
+    double* d_red = nullptr;           // reduction scratch
+    size_t red_len = 0;
+
+    // timing
+    bool profiling = false;
+    double kc_ms[dmwf::KC_COUNT] = {0, 0, 0, 0};
+    int64_t kc_n[dmwf::KC_COUNT] = {0, 0, 0, 0};
+    dmwf::GpuEvents ev;
+};
+
+namespace dmwf {
+
+// tables.cpp
+bool build_rings(const dm_grid& g, RingTables& rt, int64_t& npix, std::string& err);
+void build_coefficients(int lmax, std::vector<double>& coef, std::vector<double>& lp0,
+                        std::vector<double>& lp2);
+bool build_fft_tables(const RingTables& rt, int mmax, FftTables& ft, std::string& err);
+void build_filter(const std::vector<double>& cl, int lmax, double mu, double tau, std::vector<double>& F);
+void build_matrix_function(const std::vector<double>& cl, int lmax, int which, std::vector<double>& F);
+
+// legendre.hip
+hipError_t launch_seeds(dm_plan* p, hipStream_t s);
+// synthesis reads alm in the spin basis (T, (2)a, (-2)a)
+hipError_t launch_leg_synthesis(dm_plan* p, int nrhs, const double* spin_alm, double* phase, hipStream_t s);
+// analysis writes chunk partials of (T, (2)a, (-2)a); combine sums them,
+// converts to (T, E, B), applies the filter (may be null) and optionally
+// writes the spin-basis copy for the next synthesis (spin may be null).
+hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const double* pair_w,
+                               double* partial, hipStream_t s);
+hipError_t launch_combine(dm_plan* p, int nrhs, const double* partial, const double* filter,
+                          double* alm, double* spin, hipStream_t s);
+hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s);
+
+// ringfft.hip
+enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3 };
+// RING_ANALYSIS: map -> phase.  RING_SYNTH: phase -> map.
+// RING_ITERATE: phase -> (K x + b) -> phase.
+// RING_ITERATE with map_out != null also stores the updated messenger t.
+hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out,
+                       const double* K, const double* b, double* phase, hipStream_t s);
+hipError_t ring_set_lds_limit(size_t bytes);
+
+// pointwise.hip
+// alpha_p w_p per observed pixel, min-reduced per ring -> ring_min [nrings]
+hipError_t launch_tau_parts(dm_plan* p, const double* ncov, const uint8_t* obs, double* ring_min, hipStream_t s);
+// K, T N^-1 and N^-1 from the noise, the mask and tau
+hipError_t launch_noise_setup(dm_plan* p, const double* ncov, const uint8_t* obs, double tau, hipStream_t s);
+// d0 = mask(d), b = T N^-1 d0
+hipError_t launch_data_setup(dm_plan* p, int nrhs, const double* d, double* d0, double* b, hipStream_t s);
+// in place: ux <- N^-1 (ux - d0), b <- N^-1 d0; chi_parts [nrhs][nrings] += (d0-ux)^2 N^-1
+hipError_t launch_residual_maps(dm_plan* p, int nrhs, double* ux, const double* d0, double* b,
+                                double* chi_parts, hipStream_t s);
+// per (rhs, m, block) sums: |u-uprev|^2, |u|^2, |r|^2, |y|^2, u^T S^+ u
+constexpr int kNormQ = 5;
+int alm_norm_blocks(dm_plan* p);
+hipError_t launch_alm_norms(dm_plan* p, int nrhs, const double* u, const double* uprev, const double* r1,
+                            const double* y1, const double* mats, double* parts, hipStream_t s);
+hipError_t launch_count_nonfinite(const double* x, int64_t n, int* count, hipStream_t s);
+// y = a * x + c * y  (elementwise)
+hipError_t launch_axpby(double* y, const double* x, double a, double c, int64_t n, hipStream_t s);
+
+}  // namespace dmwf

@@ -1,0 +1,536 @@
+// Legendre step of the spin-0 + spin-2 spherical harmonic transforms
+// (the basis change of Algorithm 1, replacing the flat-sky eqs 12-16 on the
+// sphere): recursion seeds, synthesis (alm -> ring Fourier coefficients),
+// analysis (ring Fourier coefficients -> alm) and the per-(l, m) 3x3
+// messenger filter of eq 8, fused into the analysis epilogue.
+//
+// Functions: for a ring pair (theta, pi - theta) with x = cos(theta):
+//   lam_lm(theta)   spin-0 orthonormal Legendre function,
+//   p_lm = (+2)lam_lm, q_lm = (-2)lam_lm   spin +-2 functions,
+// with lam(pi - theta) = (-1)^(l+m) lam(theta) and p(pi - theta) =
+// (-1)^(l+m) q(theta).  The two spin-2 functions are recursed separately:
+// near a pole one of them is many orders of magnitude below the other, and
+// any sum/difference form would lose it to cancellation.
+// Polarization works in the spin basis (+-2)a = -(a^E +- i a^B):
+// synthesis per m:  F^T = sum_l a^T lam,  (Q + iU)_m = sum_l (2)a p,
+//                   (Q - iU)_m = sum_l (-2)a q;
+// analysis per m (w = pixel weight, G = ring Fourier coefficients):
+//   a^T = sum_r w lam G^T,  (2)a = sum_r w p G^{Q+iU},  (-2)a = sum_r w q G^{Q-iU},
+//   a^E = -((2)a + (-2)a)/2,  a^B = i((2)a - (-2)a)/2.
+//
+// Each (m, ring pair) starts its recursion at the first l where one of
+// lam, p, q exceeds 2^-100 (all earlier terms are below that and are
+// skipped).  The seeds at that l are found once per plan by a recursion
+// that carries an explicit binary exponent (the values at l = m underflow
+// double precision near the poles for large m).
+#include "dmwf_internal.h"
+
+namespace dmwf {
+
+namespace {
+
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kThr = 7.888609052210118e-31;   // 2^-100
+
+__device__ __forceinline__ int64_t mbase(int m, int lmax) {
+    return (int64_t)m * (2 * lmax + 1 - m) / 2;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct LegArgs {
+    int lmax, mmax, npairs;
+    int64_t nalm;
+    const double* __restrict__ pair_x;
+    const double* __restrict__ coef;
+    const int* __restrict__ lstart;
+    const double* __restrict__ seed;
+    int64_t sstride;      // (mmax + 1) * npairs
+};
+
+LegArgs leg_args(dm_plan* p) {
+    LegArgs a;
+    a.lmax = p->lmax;
+    a.mmax = p->mmax;
+    a.npairs = p->npairs;
+    a.nalm = p->nalm;
+    a.pair_x = p->d_pair_x;
+    a.coef = p->d_coef;
+    a.lstart = p->d_lstart;
+    a.seed = p->d_seed;
+    a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// seeds
+// ---------------------------------------------------------------------------
+__global__ void seed_kernel(int lmax, int npairs, const double* __restrict__ pair_x,
+                            const double* __restrict__ coef, const double* __restrict__ lp0,
+                            const double* __restrict__ lp2, int* __restrict__ lstart,
+                            double* __restrict__ seed, int64_t sstride) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (p >= npairs) return;
+    const double x = pair_x[p];
+    const double s = sqrt((1.0 - x) * (1.0 + x));
+    const int64_t o = (int64_t)m * npairs + p;
+    double v[6];
+    int ls;
+    if (m < 2) {
+        // spin-0 from l = m; spin-2 slots hold (l = 1, l = 2)
+        const double fourpi = 4.0 * M_PI;
+        ls = m;
+        v[0] = 0.0;
+        v[1] = (m == 0) ? 1.0 / sqrt(fourpi) : -sqrt(3.0 / (2.0 * fourpi)) * s;
+        v[2] = 0.0;
+        v[3] = (m == 0) ? sqrt(15.0 / (8.0 * fourpi)) * s * s : -sqrt(5.0 / (4.0 * fourpi)) * s * (1.0 - x);
+        v[4] = 0.0;
+        v[5] = (m == 0) ? sqrt(15.0 / (8.0 * fourpi)) * s * s : sqrt(5.0 / (4.0 * fourpi)) * s * (1.0 + x);
+    } else {
+        // l = m:  lam = (-1)^m e^{lp0} s^m,
+        //         p = (-1)^m e^{lp2} (s/2)^(m-2) (1 - x)^2 / 4,
+        //         q = (-1)^m e^{lp2} (s/2)^(m-2) (1 + x)^2 / 4
+        const double lsn = log(s);
+        const double logl = lp0[m] + m * lsn;
+        const double logw = lp2[m] + (m - 2) * (lsn - kLn2);
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        int E = (int)floor(fmax(logl, logw) / kLn2);
+        double cl = sg * exp(logl - E * kLn2);
+        const double ew = sg * exp(logw - E * kLn2) * 0.25;
+        double cw = ew * (1.0 - x) * (1.0 - x);
+        double cx = ew * (1.0 + x) * (1.0 + x);
+        double pl = 0.0, pw = 0.0, px = 0.0;
+        const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+        int l = m;
+        for (;;) {
+            const double mx = fmax(fabs(cl), fmax(fabs(cw), fabs(cx)));
+            if (E > -1200 && ldexp(mx, E) > kThr) break;
+            if (l == lmax) { l = lmax + 1; break; }
+            const double* c = coef + (base + l + 1) * kCoefStride;
+            const double ax = c[0] * x, bx = c[2] * x;
+            const double nl = ax * cl - c[1] * pl;
+            const double nw = (bx + c[3]) * cw - c[4] * pw;
+            const double nx = (bx - c[3]) * cx - c[4] * px;
+            pl = cl; pw = cw; px = cx;
+            cl = nl; cw = nw; cx = nx;
+            ++l;
+            const double m2 = fmax(fabs(cl), fmax(fabs(cw), fabs(cx)));
+            if (m2 > 0x1p400) {
+                cl *= 0x1p-400; cw *= 0x1p-400; cx *= 0x1p-400;
+                pl *= 0x1p-400; pw *= 0x1p-400; px *= 0x1p-400;
+                E += 400;
+            }
+        }
+        ls = l;
+        if (l <= lmax) {
+            v[0] = ldexp(pl, E); v[1] = ldexp(cl, E);
+            v[2] = ldexp(pw, E); v[3] = ldexp(cw, E);
+            v[4] = ldexp(px, E); v[5] = ldexp(cx, E);
+        } else {
+            for (int k = 0; k < 6; ++k) v[k] = 0.0;
+        }
+    }
+    lstart[o] = ls;
+    for (int k = 0; k < 6; ++k) seed[k * sstride + o] = v[k];
+}
+
+// One recursion step to degree l for R ring pairs: lam (l0, l1),
+// p = (+2)lam (w0, w1), q = (-2)lam (q0, q1) hold degrees (l-2, l-1).
+template <int R>
+__device__ __forceinline__ void advance(const double* __restrict__ c, const double* x, double* l0,
+                                        double* l1, double* w0, double* w1, double* q0, double* q1) {
+    const double A0 = c[0], B0 = c[1], al = c[2], ab = c[3], ga = c[4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double ax = A0 * x[r], bx = al * x[r];
+        const double nl = ax * l1[r] - B0 * l0[r];
+        const double nw = (bx + ab) * w1[r] - ga * w0[r];
+        const double nq = (bx - ab) * q1[r] - ga * q0[r];
+        l0[r] = l1[r]; l1[r] = nl;
+        w0[r] = w1[r]; w1[r] = nw;
+        q0[r] = q1[r]; q1[r] = nq;
+    }
+}
+
+// Activation of lanes whose recursion starts at degree l.
+template <int R>
+__device__ __forceinline__ void activate(const LegArgs& A, int m, int l, const int* ls, const int* pr,
+                                         double* l0, double* l1, double* w0, double* w1, double* q0,
+                                         double* q1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t o = (int64_t)m * A.npairs + pr[r];
+        if (l == ls[r]) {
+            l0[r] = A.seed[0 * A.sstride + o];
+            l1[r] = A.seed[1 * A.sstride + o];
+            if (m >= 2) {
+                w0[r] = A.seed[2 * A.sstride + o];
+                w1[r] = A.seed[3 * A.sstride + o];
+                q0[r] = A.seed[4 * A.sstride + o];
+                q1[r] = A.seed[5 * A.sstride + o];
+            }
+        }
+        if (m < 2 && l == 2 && ls[r] <= A.lmax) {
+            w0[r] = A.seed[2 * A.sstride + o];
+            w1[r] = A.seed[3 * A.sstride + o];
+            q0[r] = A.seed[4 * A.sstride + o];
+            q1[r] = A.seed[5 * A.sstride + o];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// synthesis: alm [B][3][nalm] complex -> phase [B][3][npairs][mmax+1][2]
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2* __restrict__ alm,
+                                                        double2* __restrict__ phase) {
+    const int m = blockIdx.y;
+    const int rhs = blockIdx.z;
+    const int lmax = A.lmax;
+    const int64_t base = mbase(m, lmax);
+    const double2* __restrict__ aT = alm + (int64_t)rhs * 3 * A.nalm + base;
+    const double2* __restrict__ aE = aT + A.nalm;
+    const double2* __restrict__ aB = aE + A.nalm;
+    const int nt = blockDim.x, tid = threadIdx.x;
+
+    int pr[R], ls[R];
+    double x[R], l0[R], l1[R], w0[R], w1[R], q0[R], q1[R];
+    double acc[R][20];
+    int lo = lmax + 1, hi = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        pr[r] = (blockIdx.x * R + r) * nt + tid;
+        const bool ok = pr[r] < A.npairs;
+        x[r] = ok ? A.pair_x[pr[r]] : 0.0;
+        ls[r] = ok ? A.lstart[(int64_t)m * A.npairs + pr[r]] : lmax + 1;
+        if (!ok) pr[r] = 0;
+        l0[r] = l1[r] = w0[r] = w1[r] = q0[r] = q1[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 20; ++k) acc[r][k] = 0.0;
+        lo = min(lo, ls[r]);
+        hi = max(hi, ls[r] <= lmax ? ls[r] : 0);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (m < 2) hi = max(hi, 2);
+
+    for (int l = lo; l <= lmax; ++l) {
+        if (l > lo) advance<R>(A.coef + (base + l) * kCoefStride, x, l0, l1, w0, w1, q0, q1);
+        if (l <= hi) activate<R>(A, m, l, ls, pr, l0, l1, w0, w1, q0, q1);
+        const double2 t = aT[l], e = aE[l], b = aB[l];    // a^T, (2)a, (-2)a
+        if ((l + m) & 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r][10] += l1[r] * t.x; acc[r][11] += l1[r] * t.y;
+                acc[r][12] += w1[r] * e.x; acc[r][13] += w1[r] * e.y;     // (2)a p
+                acc[r][14] += q1[r] * b.x; acc[r][15] += q1[r] * b.y;     // (-2)a q
+                acc[r][16] += q1[r] * e.x; acc[r][17] += q1[r] * e.y;     // (2)a q
+                acc[r][18] += w1[r] * b.x; acc[r][19] += w1[r] * b.y;     // (-2)a p
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r][0] += l1[r] * t.x; acc[r][1] += l1[r] * t.y;
+                acc[r][2] += w1[r] * e.x; acc[r][3] += w1[r] * e.y;
+                acc[r][4] += q1[r] * b.x; acc[r][5] += q1[r] * b.y;
+                acc[r][6] += q1[r] * e.x; acc[r][7] += q1[r] * e.y;
+                acc[r][8] += w1[r] * b.x; acc[r][9] += w1[r] * b.y;
+            }
+        }
+    }
+
+    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int p = (blockIdx.x * R + r) * nt + tid;
+        if (p >= A.npairs) continue;
+        const double* e = acc[r];       // even l+m: [0..9], odd: [10..19]
+        // T on the north and south rings
+        const double TNr = e[0] + e[10], TNi = e[1] + e[11];
+        const double TSr = e[0] - e[10], TSi = e[1] - e[11];
+        // (Q + iU) = P, (Q - iU) = M; south ring: p(pi-theta) = (-1)^(l+m) q(theta)
+        const double PNr = e[2] + e[12], PNi = e[3] + e[13];
+        const double MNr = e[4] + e[14], MNi = e[5] + e[15];
+        const double PSr = e[6] - e[16], PSi = e[7] - e[17];
+        const double MSr = e[8] - e[18], MSi = e[9] - e[19];
+        // Q = (P + M)/2, U = (P - M)/(2i)
+        double2* out = phase + (((int64_t)rhs * 3) * A.npairs + p) * (A.mmax + 1) * 2 + (int64_t)m * 2;
+        out[0] = make_double2(TNr, TNi);
+        out[1] = make_double2(TSr, TSi);
+        out += fstride;
+        out[0] = make_double2(0.5 * (PNr + MNr), 0.5 * (PNi + MNi));
+        out[1] = make_double2(0.5 * (PSr + MSr), 0.5 * (PSi + MSi));
+        out += fstride;
+        out[0] = make_double2(0.5 * (PNi - MNi), -0.5 * (PNr - MNr));
+        out[1] = make_double2(0.5 * (PSi - MSi), -0.5 * (PSr - MSr));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// analysis: phase -> partial sums [chunk][B][3][nalm] complex
+// ---------------------------------------------------------------------------
+constexpr int kAnaThreads = 256;
+constexpr int kAnaL = 4;                       // degrees per LDS reduction round
+constexpr int kAnaRow = kAnaThreads + 1;       // padded LDS row
+
+template <int R>
+__global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, const double2* __restrict__ phase,
+                                                                   const double* __restrict__ pair_w,
+                                                                   double* __restrict__ partial) {
+    __shared__ double red[kAnaL * 6 * kAnaRow];
+    __shared__ int s_lo[kAnaThreads / 64], s_hi[kAnaThreads / 64];
+    const int m = blockIdx.y;
+    const int rhs = blockIdx.z;
+    const int nrhs = gridDim.z;
+    const int chunk = blockIdx.x;
+    const int lmax = A.lmax;
+    const int64_t base = mbase(m, lmax);
+    const int tid = threadIdx.x;
+
+    int pr[R], ls[R];
+    double x[R], l0[R], l1[R], w0[R], w1[R], q0[R], q1[R];
+    // weighted ring data: T sum/difference; P = Q + iU and M = Q - iU on
+    // the north (Qs, Us) and south (Qa, Ua) rings
+    double Ts[R][2], Ta[R][2], Qs[R][2], Qa[R][2], Us[R][2], Ua[R][2];
+    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
+    int lo = lmax + 1, hi = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int p = (chunk * R + r) * kAnaThreads + tid;
+        const bool ok = p < A.npairs;
+        pr[r] = ok ? p : 0;
+        x[r] = ok ? A.pair_x[p] : 0.0;
+        ls[r] = ok ? A.lstart[(int64_t)m * A.npairs + p] : lmax + 1;
+        l0[r] = l1[r] = w0[r] = w1[r] = q0[r] = q1[r] = 0.0;
+        double2 g[3][2];
+        if (ok) {
+            const double2* in = phase + (((int64_t)rhs * 3) * A.npairs + p) * (A.mmax + 1) * 2 + (int64_t)m * 2;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                g[f][0] = in[f * fstride];
+                g[f][1] = in[f * fstride + 1];
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) g[f][0] = g[f][1] = make_double2(0.0, 0.0);
+        }
+        const double w = ok ? pair_w[p] : 0.0;
+        // T: weighted sum / difference of the two rings; polarization as
+        // P = G^Q + i G^U and M = G^Q - i G^U on each ring
+        Ts[r][0] = w * (g[0][0].x + g[0][1].x); Ts[r][1] = w * (g[0][0].y + g[0][1].y);
+        Ta[r][0] = w * (g[0][0].x - g[0][1].x); Ta[r][1] = w * (g[0][0].y - g[0][1].y);
+        Qs[r][0] = w * (g[1][0].x - g[2][0].y); Qs[r][1] = w * (g[1][0].y + g[2][0].x);   // P north
+        Qa[r][0] = w * (g[1][1].x - g[2][1].y); Qa[r][1] = w * (g[1][1].y + g[2][1].x);   // P south
+        Us[r][0] = w * (g[1][0].x + g[2][0].y); Us[r][1] = w * (g[1][0].y - g[2][0].x);   // M north
+        Ua[r][0] = w * (g[1][1].x + g[2][1].y); Ua[r][1] = w * (g[1][1].y - g[2][1].x);   // M south
+        lo = min(lo, ls[r]);
+        hi = max(hi, ls[r] <= lmax ? ls[r] : 0);
+    }
+    // block-wide range of degrees (barriers inside the loop need it uniform)
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((tid & 63) == 0) { s_lo[tid >> 6] = lo; s_hi[tid >> 6] = hi; }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int w = 1; w < kAnaThreads / 64; ++w) { lo = min(lo, s_lo[w]); hi = max(hi, s_hi[w]); }
+    if (m < 2) hi = max(hi, 2);
+
+    double* out = partial + ((((int64_t)chunk * nrhs + rhs) * 3) * A.nalm) * 2;
+    // degrees below the block's first active one get zero partial sums
+    const int lz = min(lo, lmax + 1);
+    for (int q = tid; q < (lz - m) * 6; q += kAnaThreads) {
+        const int l = m + q / 6, k = q % 6;
+        out[((int64_t)(k >> 1) * A.nalm + base + l) * 2 + (k & 1)] = 0.0;
+    }
+
+    int lchunk = lo;
+    for (int l = lo; l <= lmax; ++l) {
+        if (l > lo) advance<R>(A.coef + (base + l) * kCoefStride, x, l0, l1, w0, w1, q0, q1);
+        if (l <= hi) activate<R>(A, m, l, ls, pr, l0, l1, w0, w1, q0, q1);
+        // c = (T, (2)a, (-2)a) contributions:  (2)a += p P_N + eps q P_S,
+        // (-2)a += q M_N + eps p M_S,  eps = (-1)^(l+m)
+        double c[6] = {0, 0, 0, 0, 0, 0};
+        if ((l + m) & 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                c[0] += l1[r] * Ta[r][0]; c[1] += l1[r] * Ta[r][1];
+                c[2] += w1[r] * Qs[r][0] - q1[r] * Qa[r][0];
+                c[3] += w1[r] * Qs[r][1] - q1[r] * Qa[r][1];
+                c[4] += q1[r] * Us[r][0] - w1[r] * Ua[r][0];
+                c[5] += q1[r] * Us[r][1] - w1[r] * Ua[r][1];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                c[0] += l1[r] * Ts[r][0]; c[1] += l1[r] * Ts[r][1];
+                c[2] += w1[r] * Qs[r][0] + q1[r] * Qa[r][0];
+                c[3] += w1[r] * Qs[r][1] + q1[r] * Qa[r][1];
+                c[4] += q1[r] * Us[r][0] + w1[r] * Ua[r][0];
+                c[5] += q1[r] * Us[r][1] + w1[r] * Ua[r][1];
+            }
+        }
+        const int j = l - lchunk;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) red[(j * 6 + k) * kAnaRow + tid] = c[k];
+        if (j == kAnaL - 1 || l == lmax) {
+            __syncthreads();
+            const int nout = (j + 1) * 6;
+            const int o = tid >> 2, q = tid & 3;
+            double s = 0.0;
+            if (o < nout) {
+                const double* row = red + o * kAnaRow;
+#pragma unroll 8
+                for (int i = 0; i < kAnaThreads / 4; ++i) s += row[i * 4 + q];
+            }
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            if (o < nout && q == 0) {
+                const int ll = lchunk + o / 6, k = o % 6;
+                out[((int64_t)(k >> 1) * A.nalm + base + ll) * 2 + (k & 1)] = s;
+            }
+            __syncthreads();
+            lchunk = l + 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// combine chunk partials, convert the spin-2 pair to E/B, apply the
+// messenger filter (eq 8); optionally also write the filtered result in the
+// spin basis (T, (2)a, (-2)a) that the synthesis consumes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void eb_to_spin(double2 e, double2 b, double2& p2, double2& m2) {
+    // (+-2)a = -(E +- i B)
+    p2 = make_double2(-(e.x - b.y), -(e.y + b.x));
+    m2 = make_double2(-(e.x + b.y), -(e.y - b.x));
+}
+
+__global__ void combine_kernel(int lmax, int64_t nalm, int nchunks, int nrhs, const double2* __restrict__ partial,
+                               const double* __restrict__ filt, double2* __restrict__ alm,
+                               double2* __restrict__ spin) {
+    const int m = blockIdx.y;
+    const int rhs = blockIdx.z;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax) return;
+    const int64_t idx = mbase(m, lmax) + l;
+    double2 a[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int c = 0; c < nchunks; ++c) {
+            const double2 v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        a[f] = s;
+    }
+    // E = -((2)a + (-2)a)/2,  B = i((2)a - (-2)a)/2
+    double2 E = make_double2(-0.5 * (a[1].x + a[2].x), -0.5 * (a[1].y + a[2].y));
+    double2 B = make_double2(-0.5 * (a[1].y - a[2].y), 0.5 * (a[1].x - a[2].x));
+    if (l < 2) E = B = make_double2(0.0, 0.0);
+    double2 T = a[0];
+    if (filt) {
+        const double ftt = filt[4 * l], fte = filt[4 * l + 1], fee = filt[4 * l + 2], fbb = filt[4 * l + 3];
+        const double2 t2 = make_double2(ftt * T.x + fte * E.x, ftt * T.y + fte * E.y);
+        const double2 e2 = make_double2(fte * T.x + fee * E.x, fte * T.y + fee * E.y);
+        B = make_double2(fbb * B.x, fbb * B.y);
+        T = t2;
+        E = e2;
+    }
+    double2* o = alm + ((int64_t)rhs * 3) * nalm + idx;
+    o[0] = T;
+    o[nalm] = E;
+    o[2 * nalm] = B;
+    if (spin) {
+        double2* q = spin + ((int64_t)rhs * 3) * nalm + idx;
+        double2 p2, m2;
+        eb_to_spin(E, B, p2, m2);
+        q[0] = T;
+        q[nalm] = p2;
+        q[2 * nalm] = m2;
+    }
+}
+
+// (T, E, B) -> (T, (2)a, (-2)a)
+__global__ void to_spin_kernel(int64_t nalm, int64_t total, const double2* __restrict__ alm,
+                               double2* __restrict__ spin) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rhs = i / nalm, idx = i % nalm;
+        const double2* a = alm + rhs * 3 * nalm + idx;
+        double2* q = spin + rhs * 3 * nalm + idx;
+        double2 p2, m2;
+        eb_to_spin(a[nalm], a[2 * nalm], p2, m2);
+        q[0] = a[0];
+        q[nalm] = p2;
+        q[2 * nalm] = m2;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_seeds(dm_plan* p, hipStream_t s) {
+    dim3 grid((p->npairs + 127) / 128, p->mmax + 1);
+    hipLaunchKernelGGL(seed_kernel, grid, dim3(128), 0, s, p->lmax, p->npairs, p->d_pair_x, p->d_coef,
+                       p->d_lp0, p->d_lp2, p->d_lstart, p->d_seed, (int64_t)(p->mmax + 1) * p->npairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_synthesis(dm_plan* p, int nrhs, const double* alm, double* phase, hipStream_t s) {
+    LegArgs A = leg_args(p);
+    const int nt = p->syn_threads, R = p->syn_R;
+    dim3 grid((p->npairs + nt * R - 1) / (nt * R), p->mmax + 1, nrhs);
+    const double2* a = reinterpret_cast<const double2*>(alm);
+    double2* ph = reinterpret_cast<double2*>(phase);
+    if (R == 1) hipLaunchKernelGGL(leg_synth_kernel<1>, grid, dim3(nt), 0, s, A, a, ph);
+    else if (R == 2) hipLaunchKernelGGL(leg_synth_kernel<2>, grid, dim3(nt), 0, s, A, a, ph);
+    else hipLaunchKernelGGL(leg_synth_kernel<4>, grid, dim3(nt), 0, s, A, a, ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const double* pair_w, double* partial,
+                               hipStream_t s) {
+    LegArgs A = leg_args(p);
+    const int R = p->ana_R;
+    dim3 grid(p->ana_chunks, p->mmax + 1, nrhs);
+    const double2* ph = reinterpret_cast<const double2*>(phase);
+    if (R == 1) hipLaunchKernelGGL(leg_analysis_kernel<1>, grid, dim3(kAnaThreads), 0, s, A, ph, pair_w, partial);
+    else if (R == 2) hipLaunchKernelGGL(leg_analysis_kernel<2>, grid, dim3(kAnaThreads), 0, s, A, ph, pair_w, partial);
+    else hipLaunchKernelGGL(leg_analysis_kernel<4>, grid, dim3(kAnaThreads), 0, s, A, ph, pair_w, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(dm_plan* p, int nrhs, const double* partial, const double* filter, double* alm,
+                          double* spin, hipStream_t s) {
+    dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
+    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, s, p->lmax, p->nalm, p->ana_chunks, nrhs,
+                       reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
+                       reinterpret_cast<double2*>(spin));
+    return hipGetLastError();
+}
+
+hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s) {
+    const int64_t total = (int64_t)nrhs * p->nalm;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(to_spin_kernel, dim3((int)g), dim3(256), 0, s, p->nalm, total,
+                       reinterpret_cast<const double2*>(alm), reinterpret_cast<double2*>(spin));
+    return hipGetLastError();
+}
+
+int analysis_threads() { return kAnaThreads; }
+
+}  // namespace dmwf

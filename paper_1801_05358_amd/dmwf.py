@@ -1,0 +1,275 @@
+"""ctypes binding of libdmwf (include/dmwf.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Host calls take NumPy arrays (maps float64 [nrhs, 3, npix] in RING
+order with fields I, Q, U; alm complex128 [nrhs, 3, nalm] packed m-major with
+fields T, E, B).  Device calls take torch tensors on the GPU (float64, and
+alm as float64 [..., 2] or complex128) plus an optional torch stream.
+
+The library must have been built (``python -m paper_1801_05358_amd.build``);
+importing this module without it raises, so that no caller silently falls
+back to anything else.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmwf.so")
+
+DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
+                -5: "DM_ESTATE", -6: "DM_EUNSUPPORTED"}
+GRID_HEALPIX, GRID_GL = 0, 1
+FP64, MIXED = 0, 1
+NCOV_DIAG3 = 0
+KERNEL_CLASSES = ("legendre_analysis", "legendre_synthesis", "ring_fft_pointwise", "combine_filter")
+
+
+class DmGrid(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nside", ctypes.c_int), ("ntheta", ctypes.c_int), ("nphi", ctypes.c_int)]
+
+
+class DmSchedule(ctypes.Structure):
+    _fields_ = [("lambda_start", ctypes.c_double), ("nsteps", ctypes.c_int), ("iters_per_step", ctypes.c_int)]
+
+
+class DmStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("residual", ctypes.c_double), ("cauchy", ctypes.c_double),
+                ("chi2", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DmwfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load libdmwf.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1801_05358_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "dm_abi_version": (ctypes.c_int, []),
+        "dm_device_count": (ctypes.c_int, []),
+        "dm_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(DmGrid), ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int]),
+        "dm_plan_destroy": (ctypes.c_int, [_P]),
+        "dm_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int)]),
+        "dm_set_spectra": (ctypes.c_int, [_P, _D]),
+        "dm_set_noise": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]),
+        "dm_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(DmSchedule)]),
+        "dm_wiener_filter": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, ctypes.POINTER(DmStats)]),
+        "dm_wiener_filter_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
+        "dm_constrained_realizations": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, _D, _D]),
+        "dm_alm2map": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
+        "dm_map2alm": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
+        "dm_alm2map_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
+        "dm_alm2map_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+        "dm_map2alm_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+        "dm_iterate": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]),
+        "dm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+        "dm_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]),
+        "dm_last_error": (ctypes.c_char_p, [_P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names declared in include/dmwf.h that the binding expects."""
+    return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
+            "dm_set_spectra", "dm_set_noise", "dm_set_schedule", "dm_wiener_filter", "dm_wiener_filter_device",
+            "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
+            "dm_map2alm_device", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
+
+
+def device_count():
+    return lib().dm_device_count()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _c64(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a.reshape(shape)
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(shape)
+
+
+class Plan:
+    """A solver plan: grid, band limit, batch capacity, precision, device."""
+
+    def __init__(self, lmax, nside=None, ntheta=None, nphi=None, max_rhs=1, precision=FP64, device=0):
+        L = lib()
+        g = DmGrid()
+        if nside is not None:
+            g.kind, g.nside = GRID_HEALPIX, int(nside)
+        else:
+            g.kind, g.ntheta, g.nphi = GRID_GL, int(ntheta), int(nphi)
+        h = _P()
+        st = L.dm_plan_create(ctypes.byref(h), ctypes.byref(g), int(lmax), int(max_rhs), int(precision), int(device))
+        if st != DM_OK:
+            raise DmwfError(st, L.dm_last_error(None).decode())
+        self._h = h
+        self.lmax = int(lmax)
+        self.max_rhs = int(max_rhs)
+        npix, nalm, nr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        L.dm_plan_info(h, ctypes.byref(npix), ctypes.byref(nalm), ctypes.byref(nr))
+        self.npix, self.nalm, self.nrings = npix.value, nalm.value, nr.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != DM_OK:
+            raise DmwfError(st, lib().dm_last_error(self._h).decode())
+
+    # -- setup -------------------------------------------------------------
+    def set_spectra(self, cl):
+        cl = _f64(cl, (4, self.lmax + 1))
+        self._check(lib().dm_set_spectra(self._h, _dptr(cl)))
+
+    def set_noise(self, ncov, obs=None):
+        ncov = _f64(ncov, (3, self.npix))
+        optr = None
+        if obs is not None:
+            obs = np.ascontiguousarray(np.asarray(obs).astype(np.uint8).reshape(self.npix))
+            optr = obs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        self._check(lib().dm_set_noise(self._h, _dptr(ncov), NCOV_DIAG3, optr))
+
+    def set_schedule(self, lambda_start=1e3, nsteps=20, iters_per_step=10):
+        s = DmSchedule(float(lambda_start), int(nsteps), int(iters_per_step))
+        self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
+
+    # -- solves ------------------------------------------------------------
+    def wiener_filter(self, d, want_map=False, want_stats=False):
+        d = np.asarray(d, dtype=np.float64)
+        nrhs = 1 if d.ndim == 2 else d.shape[0]
+        d = _f64(d, (nrhs, 3, self.npix))
+        alm = np.empty((nrhs, 3, self.nalm), dtype=np.complex128)
+        mp = np.empty((nrhs, 3, self.npix)) if want_map else None
+        stats = (DmStats * nrhs)() if want_stats else None
+        self._check(lib().dm_wiener_filter(self._h, nrhs, _dptr(d), alm.ctypes.data_as(_D),
+                                           _dptr(mp) if mp is not None else None, stats))
+        out = {"alm": alm}
+        if mp is not None:
+            out["map"] = mp
+        if stats is not None:
+            out["stats"] = [s.as_dict() for s in stats]
+        return out
+
+    def wiener_filter_device(self, d, alm, map=None, stream=None, want_stats=False):
+        """d: torch float64 [nrhs, 3, npix] on the GPU; alm: torch tensor of
+        nrhs*3*nalm complex doubles; map: optional torch [nrhs, 3, npix]."""
+        nrhs = d.shape[0]
+        stats = (DmStats * nrhs)() if want_stats else None
+        sp = _P(stream.cuda_stream) if stream is not None else None
+        self._check(lib().dm_wiener_filter_device(self._h, nrhs, _P(d.data_ptr()), _P(alm.data_ptr()),
+                                                  _P(map.data_ptr()) if map is not None else None, sp, stats))
+        return [s.as_dict() for s in stats] if stats is not None else None
+
+    def constrained_realizations(self, d, shat, dhat, want_f=False):
+        nreal = shat.shape[0]
+        d = _f64(d, (3, self.npix))
+        shat = _c64(shat, (nreal, 3, self.nalm))
+        dhat = _f64(dhat, (nreal, 3, self.npix))
+        scr = np.empty((nreal, 3, self.nalm), dtype=np.complex128)
+        f = np.empty_like(scr) if want_f else None
+        self._check(lib().dm_constrained_realizations(self._h, nreal, _dptr(d), shat.ctypes.data_as(_D), _dptr(dhat),
+                                                      scr.ctypes.data_as(_D),
+                                                      f.ctypes.data_as(_D) if f is not None else None))
+        return (scr, f) if want_f else scr
+
+    # -- single transforms -------------------------------------------------
+    def alm2map(self, alm):
+        alm = np.asarray(alm)
+        nrhs = 1 if alm.ndim == 2 else alm.shape[0]
+        a = _c64(alm, (nrhs, 3, self.nalm))
+        out = np.empty((nrhs, 3, self.npix))
+        self._check(lib().dm_alm2map(self._h, nrhs, a.ctypes.data_as(_D), _dptr(out)))
+        return out if alm.ndim == 3 else out[0]
+
+    def _m2a(self, fn, m):
+        m = np.asarray(m, dtype=np.float64)
+        nrhs = 1 if m.ndim == 2 else m.shape[0]
+        mm = _f64(m, (nrhs, 3, self.npix))
+        out = np.empty((nrhs, 3, self.nalm), dtype=np.complex128)
+        self._check(fn(self._h, nrhs, _dptr(mm), out.ctypes.data_as(_D)))
+        return out if m.ndim == 3 else out[0]
+
+    def map2alm(self, m):
+        return self._m2a(lib().dm_map2alm, m)
+
+    def adjoint(self, m):
+        return self._m2a(lib().dm_alm2map_adjoint, m)
+
+    def alm2map_device(self, alm, map, stream=None):
+        sp = _P(stream.cuda_stream) if stream is not None else None
+        self._check(lib().dm_alm2map_device(self._h, alm.shape[0], _P(alm.data_ptr()), _P(map.data_ptr()), sp))
+
+    def map2alm_device(self, map, alm, stream=None):
+        sp = _P(stream.cuda_stream) if stream is not None else None
+        self._check(lib().dm_map2alm_device(self._h, map.shape[0], _P(map.data_ptr()), _P(alm.data_ptr()), sp))
+
+    def iterate(self, d, t, lam, niter):
+        d = np.asarray(d, dtype=np.float64)
+        nrhs = 1 if d.ndim == 2 else d.shape[0]
+        dd = _f64(d, (nrhs, 3, self.npix))
+        tt = _f64(t, (nrhs, 3, self.npix))
+        alm = np.empty((nrhs, 3, self.nalm), dtype=np.complex128)
+        tout = np.empty((nrhs, 3, self.npix))
+        self._check(lib().dm_iterate(self._h, nrhs, _dptr(dd), _dptr(tt), float(lam), int(niter),
+                                     alm.ctypes.data_as(_D), _dptr(tout)))
+        if d.ndim == 2:
+            return alm[0], tout[0]
+        return alm, tout
+
+    # -- profiling ---------------------------------------------------------
+    def profile(self, enable=True):
+        self._check(lib().dm_profile_enable(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        cnt = ctypes.c_int(8)
+        self._check(lib().dm_kernel_times(self._h, ms, n, ctypes.byref(cnt)))
+        return {KERNEL_CLASSES[k]: (ms[k], n[k]) for k in range(min(cnt.value, len(KERNEL_CLASSES)))}
