@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -448,11 +449,20 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         dalloc(p, p->d_seed, sn * kSeedFields);
         HIPCHK(launch_seeds(p, p->stream));
 
-        // analysis tiling: ring pairs per workgroup = 256 threads x R
-        p->ana_R = p->npairs >= 1024 ? 4 : (p->npairs >= 512 ? 2 : 1);
-        p->ana_chunks = (p->npairs + 256 * p->ana_R - 1) / (256 * p->ana_R);
-        p->syn_threads = 128;
-        p->syn_R = 1;
+        // tiling of the Legendre kernels (ring pairs per lane R); the
+        // DMWF_ANA_R / DMWF_SYN_R / DMWF_SYN_THREADS environment variables
+        // override the defaults for tuning sweeps
+        auto env_int = [](const char* k, int dflt) {
+            const char* v = std::getenv(k);
+            return v ? std::atoi(v) : dflt;
+        };
+        int ar = env_int("DMWF_ANA_R", p->npairs >= 2048 ? 2 : 1);
+        if (ar != 1 && ar != 2 && ar != 4) ar = 2;
+        set_analysis_tiling(p, ar);
+        p->syn_R = env_int("DMWF_SYN_R", 1);
+        if (p->syn_R != 1 && p->syn_R != 2 && p->syn_R != 4) p->syn_R = 1;
+        p->syn_threads = env_int("DMWF_SYN_THREADS", 128);
+        if (p->syn_threads != 64 && p->syn_threads != 128 && p->syn_threads != 256) p->syn_threads = 128;
 
         // work buffers
         const size_t B = (size_t)max_rhs;

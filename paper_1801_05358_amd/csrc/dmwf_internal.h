@@ -98,7 +98,7 @@ struct dm_plan {
     double* d_lp2 = nullptr;           // [mmax+1] log seed prefactors, spin 2
 
     // analysis tiling
-    int ana_threads = 256, ana_R = 2, ana_chunks = 1;
+    int ana_R = 2, ana_blocks = 1, ana_chunks = 1;   // chunks = partial-sum slots
     int syn_threads = 128, syn_R = 1;
     int fft_threads = 512;
     size_t fft_lds_bytes = 0;
@@ -167,6 +167,7 @@ hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const 
 hipError_t launch_combine(dm_plan* p, int nrhs, const double* partial, const double* filter,
                           double* alm, double* spin, hipStream_t s);
 hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s);
+void set_analysis_tiling(dm_plan* p, int R);
 
 // ringfft.hip
 enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3 };

@@ -187,9 +187,60 @@ __device__ __forceinline__ void activate(const LegArgs& A, int m, int l, const i
     }
 }
 
+// Recursion state of R ring pairs held by one thread.
+template <int R>
+struct RecState {
+    double x[R], l0[R], l1[R], w0[R], w1[R], q0[R], q1[R];
+    int ls[R], pr[R];
+};
+
+template <int R>
+__device__ __forceinline__ void rec_init(RecState<R>& S, const LegArgs& A, int m, int p0, int stride, int& lo,
+                                         int& hi) {
+    lo = A.lmax + 1;
+    hi = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int p = p0 + r * stride;
+        const bool ok = p < A.npairs;
+        S.pr[r] = ok ? p : 0;
+        S.x[r] = ok ? A.pair_x[p] : 0.0;
+        S.ls[r] = ok ? A.lstart[(int64_t)m * A.npairs + p] : A.lmax + 1;
+        S.l0[r] = S.l1[r] = S.w0[r] = S.w1[r] = S.q0[r] = S.q1[r] = 0.0;
+        lo = min(lo, S.ls[r]);
+        hi = max(hi, S.ls[r] <= A.lmax ? S.ls[r] : 0);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// synthesis: alm [B][3][nalm] complex -> phase [B][3][npairs][mmax+1][2]
+// synthesis: spin-basis alm [B][3][nalm] complex -> phase [B][3][npairs][mmax+1][2]
 // ---------------------------------------------------------------------------
+// acc[r][PAR*10 + k], PAR = (l + m) & 1:  k = 0,1 a^T lam;  2,3 (2)a p;
+// 4,5 (-2)a q;  6,7 (2)a q;  8,9 (-2)a p   (re, im)
+template <int R, int PAR, bool ADV, bool ACT>
+__device__ __forceinline__ void synth_step(const LegArgs& A, int m, int l, const double* __restrict__ cf,
+                                           const double2* __restrict__ aT, const double2* __restrict__ aP,
+                                           const double2* __restrict__ aM, RecState<R>& S, double (&acc)[R][20]) {
+    if (ADV) advance<R>(cf + (int64_t)l * kCoefStride, S.x, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
+    if (ACT) activate<R>(A, m, l, S.ls, S.pr, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
+    const double2 t = aT[l], e = aP[l], b = aM[l];
+    constexpr int o = PAR * 10;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double lam = S.l1[r], pp = S.w1[r], qq = S.q1[r];
+        acc[r][o + 0] = fma(lam, t.x, acc[r][o + 0]);
+        acc[r][o + 1] = fma(lam, t.y, acc[r][o + 1]);
+        acc[r][o + 2] = fma(pp, e.x, acc[r][o + 2]);
+        acc[r][o + 3] = fma(pp, e.y, acc[r][o + 3]);
+        acc[r][o + 4] = fma(qq, b.x, acc[r][o + 4]);
+        acc[r][o + 5] = fma(qq, b.y, acc[r][o + 5]);
+        acc[r][o + 6] = fma(qq, e.x, acc[r][o + 6]);
+        acc[r][o + 7] = fma(qq, e.y, acc[r][o + 7]);
+        acc[r][o + 8] = fma(pp, b.x, acc[r][o + 8]);
+        acc[r][o + 9] = fma(pp, b.y, acc[r][o + 9]);
+    }
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2* __restrict__ alm,
                                                         double2* __restrict__ phase) {
@@ -198,60 +249,51 @@ __global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
     const double2* __restrict__ aT = alm + (int64_t)rhs * 3 * A.nalm + base;
-    const double2* __restrict__ aE = aT + A.nalm;
-    const double2* __restrict__ aB = aE + A.nalm;
+    const double2* __restrict__ aP = aT + A.nalm;
+    const double2* __restrict__ aM = aP + A.nalm;
+    const double* __restrict__ cf = A.coef + base * kCoefStride;
     const int nt = blockDim.x, tid = threadIdx.x;
 
-    int pr[R], ls[R];
-    double x[R], l0[R], l1[R], w0[R], w1[R], q0[R], q1[R];
+    RecState<R> S;
     double acc[R][20];
-    int lo = lmax + 1, hi = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        pr[r] = (blockIdx.x * R + r) * nt + tid;
-        const bool ok = pr[r] < A.npairs;
-        x[r] = ok ? A.pair_x[pr[r]] : 0.0;
-        ls[r] = ok ? A.lstart[(int64_t)m * A.npairs + pr[r]] : lmax + 1;
-        if (!ok) pr[r] = 0;
-        l0[r] = l1[r] = w0[r] = w1[r] = q0[r] = q1[r] = 0.0;
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int k = 0; k < 20; ++k) acc[r][k] = 0.0;
-        lo = min(lo, ls[r]);
-        hi = max(hi, ls[r] <= lmax ? ls[r] : 0);
-    }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    int lo, hi;
+    rec_init<R>(S, A, m, blockIdx.x * R * nt + tid, nt, lo, hi);
+    // the degree loop is uniform across the wave
+    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     if (m < 2) hi = max(hi, 2);
 
-    for (int l = lo; l <= lmax; ++l) {
-        if (l > lo) advance<R>(A.coef + (base + l) * kCoefStride, x, l0, l1, w0, w1, q0, q1);
-        if (l <= hi) activate<R>(A, m, l, ls, pr, l0, l1, w0, w1, q0, q1);
-        const double2 t = aT[l], e = aE[l], b = aB[l];    // a^T, (2)a, (-2)a
-        if ((l + m) & 1) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r][10] += l1[r] * t.x; acc[r][11] += l1[r] * t.y;
-                acc[r][12] += w1[r] * e.x; acc[r][13] += w1[r] * e.y;     // (2)a p
-                acc[r][14] += q1[r] * b.x; acc[r][15] += q1[r] * b.y;     // (-2)a q
-                acc[r][16] += q1[r] * e.x; acc[r][17] += q1[r] * e.y;     // (2)a q
-                acc[r][18] += w1[r] * b.x; acc[r][19] += w1[r] * b.y;     // (-2)a p
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r][0] += l1[r] * t.x; acc[r][1] += l1[r] * t.y;
-                acc[r][2] += w1[r] * e.x; acc[r][3] += w1[r] * e.y;
-                acc[r][4] += q1[r] * b.x; acc[r][5] += q1[r] * b.y;
-                acc[r][6] += q1[r] * e.x; acc[r][7] += q1[r] * e.y;
-                acc[r][8] += w1[r] * b.x; acc[r][9] += w1[r] * b.y;
-            }
+    int l = lo;
+    if (l <= lmax) {
+        // activation phase: some lanes start their recursion at l
+        if ((l + m) & 1) synth_step<R, 1, false, true>(A, m, l, cf, aT, aP, aM, S, acc);
+        else synth_step<R, 0, false, true>(A, m, l, cf, aT, aP, aM, S, acc);
+        ++l;
+        const int h = min(hi, lmax);
+        for (; l <= h; ++l) {
+            if ((l + m) & 1) synth_step<R, 1, true, true>(A, m, l, cf, aT, aP, aM, S, acc);
+            else synth_step<R, 0, true, true>(A, m, l, cf, aT, aP, aM, S, acc);
         }
+        // steady state: every lane active, parity unrolled
+        if (l <= lmax && ((l + m) & 1)) {
+            synth_step<R, 1, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
+            ++l;
+        }
+        for (; l + 1 <= lmax; l += 2) {
+            synth_step<R, 0, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
+            synth_step<R, 1, true, false>(A, m, l + 1, cf, aT, aP, aM, S, acc);
+        }
+        if (l <= lmax) synth_step<R, 0, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
     }
 
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int p = (blockIdx.x * R + r) * nt + tid;
+        const int p = blockIdx.x * R * nt + r * nt + tid;
         if (p >= A.npairs) continue;
         const double* e = acc[r];       // even l+m: [0..9], odd: [10..19]
         // T on the north and south rings
@@ -276,41 +318,116 @@ __global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2
 }
 
 // ---------------------------------------------------------------------------
-// analysis: phase -> partial sums [chunk][B][3][nalm] complex
+// analysis: phase -> partial sums [slot][B][3][nalm] complex of
+// (a^T, (2)a, (-2)a), one slot per wave of 64 lanes x R ring pairs.
+// Each wave reduces its own lanes through a private LDS tile every kAnaL
+// degrees, so no block-wide barrier sits inside the degree loop.
 // ---------------------------------------------------------------------------
-constexpr int kAnaThreads = 256;
-constexpr int kAnaL = 4;                       // degrees per LDS reduction round
-constexpr int kAnaRow = kAnaThreads + 1;       // padded LDS row
+constexpr int kAnaThreads = 256;               // 4 independent waves
+constexpr int kAnaL = 4;                       // degrees per reduction round
+constexpr int kAnaRow = 66;                    // padded LDS row (64 lanes)
+constexpr int kAnaTile = kAnaL * 6 * kAnaRow;  // doubles per wave
+
+// weighted ring data of R ring pairs: T sum/difference; P = Q + iU and
+// M = Q - iU on the north (n) and south (s) rings
+template <int R>
+struct AnaData {
+    double Ts[R][2], Ta[R][2], Pn[R][2], Ps[R][2], Mn[R][2], Ms[R][2];
+};
+
+// c = (a^T, (2)a, (-2)a) contributions at degree l, summed over the lane's
+// ring pairs:  (2)a += p P_n + eps q P_s,  (-2)a += q M_n + eps p M_s,
+// eps = (-1)^(l+m); written to the lane's column of the degree's rows.
+template <int R, int PAR, bool ADV, bool ACT>
+__device__ __forceinline__ void ana_step(const LegArgs& A, int m, int l, const double* __restrict__ cf,
+                                         RecState<R>& S, const AnaData<R>& D, double* slot) {
+    if (ADV) advance<R>(cf + (int64_t)l * kCoefStride, S.x, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
+    if (ACT) activate<R>(A, m, l, S.ls, S.pr, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
+    double c[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double lam = S.l1[r], pp = S.w1[r], qq = S.q1[r];
+        if (PAR) {
+            c[0] = fma(lam, D.Ta[r][0], c[0]);
+            c[1] = fma(lam, D.Ta[r][1], c[1]);
+            c[2] = fma(pp, D.Pn[r][0], fma(-qq, D.Ps[r][0], c[2]));
+            c[3] = fma(pp, D.Pn[r][1], fma(-qq, D.Ps[r][1], c[3]));
+            c[4] = fma(qq, D.Mn[r][0], fma(-pp, D.Ms[r][0], c[4]));
+            c[5] = fma(qq, D.Mn[r][1], fma(-pp, D.Ms[r][1], c[5]));
+        } else {
+            c[0] = fma(lam, D.Ts[r][0], c[0]);
+            c[1] = fma(lam, D.Ts[r][1], c[1]);
+            c[2] = fma(pp, D.Pn[r][0], fma(qq, D.Ps[r][0], c[2]));
+            c[3] = fma(pp, D.Pn[r][1], fma(qq, D.Ps[r][1], c[3]));
+            c[4] = fma(qq, D.Mn[r][0], fma(pp, D.Ms[r][0], c[4]));
+            c[5] = fma(qq, D.Mn[r][1], fma(pp, D.Ms[r][1], c[5]));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) slot[k * kAnaRow] = c[k];
+}
+
+template <int R>
+__device__ __forceinline__ void ana_step_any(const LegArgs& A, int m, int l, int lo, int hi,
+                                             const double* __restrict__ cf, RecState<R>& S, const AnaData<R>& D,
+                                             double* slot) {
+    const bool par = (l + m) & 1;
+    if (l > lo) {
+        if (l <= hi) {
+            if (par) ana_step<R, 1, true, true>(A, m, l, cf, S, D, slot);
+            else ana_step<R, 0, true, true>(A, m, l, cf, S, D, slot);
+        } else {
+            if (par) ana_step<R, 1, true, false>(A, m, l, cf, S, D, slot);
+            else ana_step<R, 0, true, false>(A, m, l, cf, S, D, slot);
+        }
+    } else {
+        if (par) ana_step<R, 1, false, true>(A, m, l, cf, S, D, slot);
+        else ana_step<R, 0, false, true>(A, m, l, cf, S, D, slot);
+    }
+}
+
+// a full round of kAnaL degrees in the steady state (no activation)
+template <int R, int P0>
+__device__ __forceinline__ void ana_round(const LegArgs& A, int m, int lc, const double* __restrict__ cf,
+                                          RecState<R>& S, const AnaData<R>& D, double* tile, int lane) {
+#pragma unroll
+    for (int j = 0; j < kAnaL; ++j) {
+        if ((P0 + j) & 1) ana_step<R, 1, true, false>(A, m, lc + j, cf, S, D, tile + j * 6 * kAnaRow + lane);
+        else ana_step<R, 0, true, false>(A, m, lc + j, cf, S, D, tile + j * 6 * kAnaRow + lane);
+    }
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int R>
 __global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, const double2* __restrict__ phase,
                                                                    const double* __restrict__ pair_w,
                                                                    double* __restrict__ partial) {
-    __shared__ double red[kAnaL * 6 * kAnaRow];
-    __shared__ int s_lo[kAnaThreads / 64], s_hi[kAnaThreads / 64];
+    __shared__ double red[(kAnaThreads / 64) * kAnaTile];
     const int m = blockIdx.y;
     const int rhs = blockIdx.z;
     const int nrhs = gridDim.z;
-    const int chunk = blockIdx.x;
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
-    const int tid = threadIdx.x;
+    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (kAnaThreads / 64) + (threadIdx.x >> 6);   // partial-sum slot
+    double* tile = red + (threadIdx.x >> 6) * kAnaTile;
+    const int p0 = wave * 64 * R + lane;
 
-    int pr[R], ls[R];
-    double x[R], l0[R], l1[R], w0[R], w1[R], q0[R], q1[R];
-    // weighted ring data: T sum/difference; P = Q + iU and M = Q - iU on
-    // the north (Qs, Us) and south (Qa, Ua) rings
-    double Ts[R][2], Ta[R][2], Qs[R][2], Qa[R][2], Us[R][2], Ua[R][2];
+    RecState<R> S;
+    AnaData<R> D;
+    int lo, hi;
+    rec_init<R>(S, A, m, p0, 64, lo, hi);
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
-    int lo = lmax + 1, hi = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int p = (chunk * R + r) * kAnaThreads + tid;
+        const int p = p0 + r * 64;
         const bool ok = p < A.npairs;
-        pr[r] = ok ? p : 0;
-        x[r] = ok ? A.pair_x[p] : 0.0;
-        ls[r] = ok ? A.lstart[(int64_t)m * A.npairs + p] : lmax + 1;
-        l0[r] = l1[r] = w0[r] = w1[r] = q0[r] = q1[r] = 0.0;
         double2 g[3][2];
         if (ok) {
             const double2* in = phase + (((int64_t)rhs * 3) * A.npairs + p) * (A.mmax + 1) * 2 + (int64_t)m * 2;
@@ -324,83 +441,50 @@ __global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, co
             for (int f = 0; f < 3; ++f) g[f][0] = g[f][1] = make_double2(0.0, 0.0);
         }
         const double w = ok ? pair_w[p] : 0.0;
-        // T: weighted sum / difference of the two rings; polarization as
-        // P = G^Q + i G^U and M = G^Q - i G^U on each ring
-        Ts[r][0] = w * (g[0][0].x + g[0][1].x); Ts[r][1] = w * (g[0][0].y + g[0][1].y);
-        Ta[r][0] = w * (g[0][0].x - g[0][1].x); Ta[r][1] = w * (g[0][0].y - g[0][1].y);
-        Qs[r][0] = w * (g[1][0].x - g[2][0].y); Qs[r][1] = w * (g[1][0].y + g[2][0].x);   // P north
-        Qa[r][0] = w * (g[1][1].x - g[2][1].y); Qa[r][1] = w * (g[1][1].y + g[2][1].x);   // P south
-        Us[r][0] = w * (g[1][0].x + g[2][0].y); Us[r][1] = w * (g[1][0].y - g[2][0].x);   // M north
-        Ua[r][0] = w * (g[1][1].x + g[2][1].y); Ua[r][1] = w * (g[1][1].y - g[2][1].x);   // M south
-        lo = min(lo, ls[r]);
-        hi = max(hi, ls[r] <= lmax ? ls[r] : 0);
+        D.Ts[r][0] = w * (g[0][0].x + g[0][1].x); D.Ts[r][1] = w * (g[0][0].y + g[0][1].y);
+        D.Ta[r][0] = w * (g[0][0].x - g[0][1].x); D.Ta[r][1] = w * (g[0][0].y - g[0][1].y);
+        D.Pn[r][0] = w * (g[1][0].x - g[2][0].y); D.Pn[r][1] = w * (g[1][0].y + g[2][0].x);
+        D.Ps[r][0] = w * (g[1][1].x - g[2][1].y); D.Ps[r][1] = w * (g[1][1].y + g[2][1].x);
+        D.Mn[r][0] = w * (g[1][0].x + g[2][0].y); D.Mn[r][1] = w * (g[1][0].y - g[2][0].x);
+        D.Ms[r][0] = w * (g[1][1].x + g[2][1].y); D.Ms[r][1] = w * (g[1][1].y - g[2][1].x);
     }
-    // block-wide range of degrees (barriers inside the loop need it uniform)
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    if ((tid & 63) == 0) { s_lo[tid >> 6] = lo; s_hi[tid >> 6] = hi; }
-    __syncthreads();
-    lo = s_lo[0];
-    hi = s_hi[0];
-    for (int w = 1; w < kAnaThreads / 64; ++w) { lo = min(lo, s_lo[w]); hi = max(hi, s_hi[w]); }
+    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     if (m < 2) hi = max(hi, 2);
 
-    double* out = partial + ((((int64_t)chunk * nrhs + rhs) * 3) * A.nalm) * 2;
-    // degrees below the block's first active one get zero partial sums
+    double* out = partial + ((((int64_t)wave * nrhs + rhs) * 3) * A.nalm) * 2;
+    // degrees below the wave's first active one get zero partial sums
     const int lz = min(lo, lmax + 1);
-    for (int q = tid; q < (lz - m) * 6; q += kAnaThreads) {
+    for (int q = lane; q < (lz - m) * 6; q += 64) {
         const int l = m + q / 6, k = q % 6;
         out[((int64_t)(k >> 1) * A.nalm + base + l) * 2 + (k & 1)] = 0.0;
     }
 
-    int lchunk = lo;
-    for (int l = lo; l <= lmax; ++l) {
-        if (l > lo) advance<R>(A.coef + (base + l) * kCoefStride, x, l0, l1, w0, w1, q0, q1);
-        if (l <= hi) activate<R>(A, m, l, ls, pr, l0, l1, w0, w1, q0, q1);
-        // c = (T, (2)a, (-2)a) contributions:  (2)a += p P_N + eps q P_S,
-        // (-2)a += q M_N + eps p M_S,  eps = (-1)^(l+m)
-        double c[6] = {0, 0, 0, 0, 0, 0};
-        if ((l + m) & 1) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                c[0] += l1[r] * Ta[r][0]; c[1] += l1[r] * Ta[r][1];
-                c[2] += w1[r] * Qs[r][0] - q1[r] * Qa[r][0];
-                c[3] += w1[r] * Qs[r][1] - q1[r] * Qa[r][1];
-                c[4] += q1[r] * Us[r][0] - w1[r] * Ua[r][0];
-                c[5] += q1[r] * Us[r][1] - w1[r] * Ua[r][1];
-            }
+    // reduction roles: 2 lanes per (degree, component) row
+    const int o = lane >> 1, q = lane & 1;
+    for (int lc = lo; lc <= lmax; lc += kAnaL) {
+        const int ln = min(kAnaL, lmax + 1 - lc);
+        if (ln == kAnaL && lc > hi) {
+            if ((lc + m) & 1) ana_round<R, 1>(A, m, lc, cf, S, D, tile, lane);
+            else ana_round<R, 0>(A, m, lc, cf, S, D, tile, lane);
         } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                c[0] += l1[r] * Ts[r][0]; c[1] += l1[r] * Ts[r][1];
-                c[2] += w1[r] * Qs[r][0] + q1[r] * Qa[r][0];
-                c[3] += w1[r] * Qs[r][1] + q1[r] * Qa[r][1];
-                c[4] += q1[r] * Us[r][0] + w1[r] * Ua[r][0];
-                c[5] += q1[r] * Us[r][1] + w1[r] * Ua[r][1];
-            }
+            for (int j = 0; j < ln; ++j)
+                ana_step_any<R>(A, m, lc + j, lo, hi, cf, S, D, tile + j * 6 * kAnaRow + lane);
         }
-        const int j = l - lchunk;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) red[(j * 6 + k) * kAnaRow + tid] = c[k];
-        if (j == kAnaL - 1 || l == lmax) {
-            __syncthreads();
-            const int nout = (j + 1) * 6;
-            const int o = tid >> 2, q = tid & 3;
-            double s = 0.0;
-            if (o < nout) {
-                const double* row = red + o * kAnaRow;
+        wave_sync();
+        const int nout = ln * 6;
+        double s = 0.0;
+        if (o < nout) {
+            const double* row = tile + o * kAnaRow + q * 32;
 #pragma unroll 8
-                for (int i = 0; i < kAnaThreads / 4; ++i) s += row[i * 4 + q];
-            }
-            s += __shfl_xor(s, 1, 64);
-            s += __shfl_xor(s, 2, 64);
-            if (o < nout && q == 0) {
-                const int ll = lchunk + o / 6, k = o % 6;
-                out[((int64_t)(k >> 1) * A.nalm + base + ll) * 2 + (k & 1)] = s;
-            }
-            __syncthreads();
-            lchunk = l + 1;
+            for (int i = 0; i < 32; ++i) s += row[i];
         }
+        s += __shfl_xor(s, 1, 64);
+        if (o < nout && q == 0) {
+            const int ll = lc + o / 6, k = o % 6;
+            out[((int64_t)(k >> 1) * A.nalm + base + ll) * 2 + (k & 1)] = s;
+        }
+        wave_sync();
     }
 }
 
@@ -505,12 +589,22 @@ hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const 
                                hipStream_t s) {
     LegArgs A = leg_args(p);
     const int R = p->ana_R;
-    dim3 grid(p->ana_chunks, p->mmax + 1, nrhs);
+    dim3 grid(p->ana_blocks, p->mmax + 1, nrhs);
     const double2* ph = reinterpret_cast<const double2*>(phase);
     if (R == 1) hipLaunchKernelGGL(leg_analysis_kernel<1>, grid, dim3(kAnaThreads), 0, s, A, ph, pair_w, partial);
     else if (R == 2) hipLaunchKernelGGL(leg_analysis_kernel<2>, grid, dim3(kAnaThreads), 0, s, A, ph, pair_w, partial);
     else hipLaunchKernelGGL(leg_analysis_kernel<4>, grid, dim3(kAnaThreads), 0, s, A, ph, pair_w, partial);
     return hipGetLastError();
+}
+
+// analysis tiling: R ring pairs per lane, 4 waves per workgroup; one
+// partial-sum slot per wave
+void set_analysis_tiling(dm_plan* p, int R) {
+    p->ana_R = R;
+    const int per_wave = 64 * R;
+    const int waves = (p->npairs + per_wave - 1) / per_wave;
+    p->ana_blocks = (waves + kAnaThreads / 64 - 1) / (kAnaThreads / 64);
+    p->ana_chunks = p->ana_blocks * (kAnaThreads / 64);
 }
 
 hipError_t launch_combine(dm_plan* p, int nrhs, const double* partial, const double* filter, double* alm,
@@ -531,6 +625,5 @@ hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin,
     return hipGetLastError();
 }
 
-int analysis_threads() { return kAnaThreads; }
 
 }  // namespace dmwf
