@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--nside", type=int, default=1024)
     ap.add_argument("--lmax", type=int, default=2048)
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -87,7 +88,8 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"[bench] workload nside={nside} lmax={lmax} nrhs={B}")
     prob = inputs.make_problem(3, nside=nside, lmax=lmax)
-    plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=B, device=0)
+    prec = dmwf.MIXED if args.precision == "mixed" else dmwf.FP64
+    plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=B, device=0, precision=prec)
     plan.set_spectra(prob["cl"])
     plan.set_noise(prob["ncov"], prob["obs"])
     dev = torch.device("cuda:0")

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdmwf.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["tables.cpp", "legendre.hip", "ringfft.hip", "pointwise.hip", "api.cpp"]
+SOURCES = ["tables.cpp", "legendre.hip", "legendre_mfma.hip", "ringfft.hip", "pointwise.hip", "api.cpp"]
 ARCH = os.environ.get("DMWF_OFFLOAD_ARCH", "gfx950")
 # packed FP32 instructions are kept off for every HIP translation unit
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

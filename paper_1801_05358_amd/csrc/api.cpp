@@ -121,22 +121,43 @@ void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const d
 
 // analysis + combine: alm = filter(A t) in (T, E, B); spin (nullable)
 // receives the same coefficients in the spin basis for the synthesis
+// batched matrix-core Legendre kernels: always for DM_MIXED, for DM_FP64
+// from 8 right-hand sides on (DMWF_MFMA=0/1 forces it off/on)
+bool use_mfma(dm_plan* p, int nrhs) {
+    if (p->precision == DM_MIXED) return true;
+    if (p->mfma_mode >= 0) return p->mfma_mode == 1;
+    return nrhs >= 8;
+}
+
 void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, const double* filter, double* alm,
                   double* spin, hipStream_t s) {
+    const double* w = weighted ? p->d_pair_w : p->d_pair_one;
+    int nslots = p->ana_chunks;
     {
         Timed t(p, KC_LEG_ANALYSIS, s);
-        HIPCHK(launch_leg_analysis(p, nrhs, phase, weighted ? p->d_pair_w : p->d_pair_one, p->d_partial, s));
+        if (use_mfma(p, nrhs)) {
+            p->mfma_nct = 1;
+            nslots = batched_analysis_slots(p);
+            HIPCHK(launch_bana(p, nrhs, phase, w, p->d_partial, s));
+        } else {
+            HIPCHK(launch_leg_analysis(p, nrhs, phase, w, p->d_partial, s));
+        }
         t.done();
     }
     Timed t(p, KC_COMBINE, s);
-    HIPCHK(launch_combine(p, nrhs, p->d_partial, filter, alm, spin, s));
+    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, filter, alm, spin, s));
     t.done();
 }
 
 // synthesis from spin-basis coefficients
 void leg_synthesis(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
     Timed t(p, KC_LEG_SYNTHESIS, s);
-    HIPCHK(launch_leg_synthesis(p, nrhs, spin, phase, s));
+    if (use_mfma(p, nrhs)) {
+        p->mfma_nct = 1;
+        HIPCHK(launch_bsyn(p, nrhs, spin, phase, s));
+    } else {
+        HIPCHK(launch_leg_synthesis(p, nrhs, spin, phase, s));
+    }
     t.done();
 }
 
@@ -363,7 +384,6 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
     try {
         HIPCHK(hipSetDevice(device));
         REQUIRE(precision == DM_FP64 || precision == DM_MIXED, DM_EINVAL, "unknown precision");
-        REQUIRE(precision == DM_FP64, DM_EUNSUPPORTED, "this build implements DM_FP64 only");
         REQUIRE(max_rhs >= 1 && max_rhs <= 4096, DM_EINVAL, "max_rhs must be in [1, 4096]");
         REQUIRE(lmax >= 2 && lmax <= 16384, DM_EINVAL, "lmax must be in [2, 16384]");
         std::string e;
@@ -463,11 +483,13 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         if (p->syn_R != 1 && p->syn_R != 2 && p->syn_R != 4) p->syn_R = 1;
         p->syn_threads = env_int("DMWF_SYN_THREADS", 128);
         if (p->syn_threads != 64 && p->syn_threads != 128 && p->syn_threads != 256) p->syn_threads = 128;
+        p->mfma_mode = env_int("DMWF_MFMA", -1);
 
         // work buffers
         const size_t B = (size_t)max_rhs;
         dalloc(p, p->d_phase, B * 3 * p->npairs * (p->mmax + 1) * 4);
-        dalloc(p, p->d_partial, (size_t)p->ana_chunks * B * 3 * p->nalm * 2);
+        const size_t slots = (size_t)std::max(p->ana_chunks, batched_analysis_slots(p));
+        dalloc(p, p->d_partial, slots * B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_prev, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_spin, B * 3 * p->nalm * 2);

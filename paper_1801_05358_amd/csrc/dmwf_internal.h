@@ -99,6 +99,8 @@ struct dm_plan {
 
     // analysis tiling
     int ana_R = 2, ana_blocks = 1, ana_chunks = 1;   // chunks = partial-sum slots
+    int mfma_nct = 1;                                 // column tiles (8 RHS each) of the batched kernels
+    int mfma_mode = -1;                               // -1 auto, 0 off, 1 on (FP64 plans)
     int syn_threads = 128, syn_R = 1;
     int fft_threads = 512;
     size_t fft_lds_bytes = 0;
@@ -164,10 +166,18 @@ hipError_t launch_leg_synthesis(dm_plan* p, int nrhs, const double* spin_alm, do
 // writes the spin-basis copy for the next synthesis (spin may be null).
 hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const double* pair_w,
                                double* partial, hipStream_t s);
-hipError_t launch_combine(dm_plan* p, int nrhs, const double* partial, const double* filter,
+hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
                           double* alm, double* spin, hipStream_t s);
 hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s);
 void set_analysis_tiling(dm_plan* p, int R);
+
+// legendre_mfma.hip: batched Legendre products on the matrix cores
+// (FP64 for DM_FP64 plans, FP32 for DM_MIXED); analysis writes one
+// partial-sum slot per block of ring pairs
+int batched_analysis_slots(dm_plan* p);
+hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s);
+hipError_t launch_bana(dm_plan* p, int nrhs, const double* phase, const double* pair_w, double* partial,
+                       hipStream_t s);
 
 // ringfft.hip
 enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3 };

@@ -607,10 +607,10 @@ void set_analysis_tiling(dm_plan* p, int R) {
     p->ana_chunks = p->ana_blocks * (kAnaThreads / 64);
 }
 
-hipError_t launch_combine(dm_plan* p, int nrhs, const double* partial, const double* filter, double* alm,
-                          double* spin, hipStream_t s) {
+hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
+                          double* alm, double* spin, hipStream_t s) {
     dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
-    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, s, p->lmax, p->nalm, p->ana_chunks, nrhs,
+    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
                        reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
                        reinterpret_cast<double2*>(spin));
     return hipGetLastError();

@@ -1,0 +1,533 @@
+// Batched Legendre step on the matrix cores: for B right-hand sides the
+// contractions of the spherical harmonic transform become dense products
+// (the batching of constrained realizations, Sec. 2.2, eq 19):
+//
+//   synthesis  Out[(pair, side), (rhs, re/im)] += sum_l A_f[(pair, side), l] D_f[l, (rhs, re/im)]
+//   analysis   Out[l, (rhs, re/im)]            += sum_(pair, side) A_f[(pair, side), l] G_f[(pair, side), (rhs, re/im)]
+//
+// with three products f = T, +2, -2 and rows (pair, side) = the north ring
+// and its mirror:  A_T = (lam, eps lam),  A_+2 = (p, eps q),
+// A_-2 = (q, eps p),  eps = (-1)^(l+m),  p = (+2)lam, q = (-2)lam.
+// D_f are the spin-basis coefficients (a^T, (2)a, (-2)a); G_f are the
+// weighted ring Fourier data (G^T, G^Q + i G^U, G^Q - i G^U).
+//
+// One lane runs the FP64 recursions of one ring pair (seeds and start
+// degrees as in the single-RHS kernels); the values of a few consecutive
+// degrees go through a double-buffered, wave-private LDS tile into the
+// operand layout of v_mfma_*_16x16x4 (A: lane = row + 16 k, B: lane =
+// col + 16 k).  T = double uses the FP64 matrix instruction; T = float
+// converts the functions and data to FP32 and accumulates in FP32 (the
+// mixed-precision path; the iterate itself stays FP64).
+#include "dmwf_internal.h"
+
+namespace dmwf {
+
+namespace {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // output element v of a lane sits at row (lane / 16) + 4 v
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // output element v of a lane sits at row 4 (lane / 16) + v
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+__device__ __forceinline__ int64_t mbase(int m, int lmax) { return (int64_t)m * (2 * lmax + 1 - m) / 2; }
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct BatchArgs {
+    int lmax, mmax, npairs, nrhs;
+    int64_t nalm;
+    const double* __restrict__ pair_x;
+    const double* __restrict__ coef;
+    const int* __restrict__ lstart;
+    const double* __restrict__ seed;
+    int64_t sstride;
+};
+
+// FP64 recursion of one ring pair: lam, p, q at (l-1, l).
+struct Rec {
+    double x, l0, l1, w0, w1, q0, q1;
+    int ls, pr;
+};
+
+__device__ __forceinline__ void rec_advance(const double* __restrict__ c, Rec& s) {
+    const double ax = c[0] * s.x, bx = c[2] * s.x;
+    const double nl = ax * s.l1 - c[1] * s.l0;
+    const double nw = (bx + c[3]) * s.w1 - c[4] * s.w0;
+    const double nq = (bx - c[3]) * s.q1 - c[4] * s.q0;
+    s.l0 = s.l1; s.l1 = nl;
+    s.w0 = s.w1; s.w1 = nw;
+    s.q0 = s.q1; s.q1 = nq;
+}
+
+__device__ __forceinline__ void rec_activate(const BatchArgs& A, int m, int l, Rec& s) {
+    const int64_t o = (int64_t)m * A.npairs + s.pr;
+    if (l == s.ls) {
+        s.l0 = A.seed[0 * A.sstride + o];
+        s.l1 = A.seed[1 * A.sstride + o];
+        if (m >= 2) {
+            s.w0 = A.seed[2 * A.sstride + o];
+            s.w1 = A.seed[3 * A.sstride + o];
+            s.q0 = A.seed[4 * A.sstride + o];
+            s.q1 = A.seed[5 * A.sstride + o];
+        }
+    }
+    if (m < 2 && l == 2 && s.ls <= A.lmax) {
+        s.w0 = A.seed[2 * A.sstride + o];
+        s.w1 = A.seed[3 * A.sstride + o];
+        s.q0 = A.seed[4 * A.sstride + o];
+        s.q1 = A.seed[5 * A.sstride + o];
+    }
+}
+
+__device__ __forceinline__ void rec_init(Rec& s, const BatchArgs& A, int m, int p) {
+    const bool ok = p < A.npairs;
+    s.pr = ok ? p : 0;
+    s.x = ok ? A.pair_x[p] : 0.0;
+    s.ls = ok ? A.lstart[(int64_t)m * A.npairs + p] : A.lmax + 1;
+    s.l0 = s.l1 = s.w0 = s.w1 = s.q0 = s.q1 = 0.0;
+}
+
+// one recursion step to degree l (zero beyond lmax)
+__device__ __forceinline__ void rec_step(const BatchArgs& A, const double* __restrict__ cf, int m, int l, int lo,
+                                         int hi, Rec& s, double& lam, double& pp, double& qq) {
+    if (l <= A.lmax) {
+        if (l > lo) rec_advance(cf + (int64_t)l * kCoefStride, s);
+        if (l <= hi) rec_activate(A, m, l, s);
+        lam = s.l1;
+        pp = s.w1;
+        qq = s.q1;
+    } else {
+        lam = pp = qq = 0.0;
+    }
+}
+
+// recursion values of the next degree for the steady state (every lane
+// past its start degree, degree <= lmax): no branch, so the compiler can
+// interleave it with the matrix instructions of the current round
+__device__ __forceinline__ void rec_next(const double* __restrict__ cf, int l, Rec& s) {
+    rec_advance(cf + (int64_t)l * kCoefStride, s);
+}
+
+// ---------------------------------------------------------------------------
+// synthesis: 4 waves x (8 RT) ring pairs per block, rounds of 4 degrees;
+// one column tile of 8 RHS per block.  The producer writes two copies of
+// the round's functions: north rows (lam, p, q) and south rows
+// eps (lam, q, p), so that every A operand is a plain LDS read.
+// ---------------------------------------------------------------------------
+constexpr int kSynWaves = 4;
+
+template <typename T, int RT>
+struct SynTile {
+    T v[2][3][4][64];            // [side][A_T, A_+2, A_-2][degree in round][pair]
+};
+
+template <typename T, int RT>
+__device__ __forceinline__ void bsyn_mfma(const SynTile<T, RT>& tl, int k, int pl, int side, const T (&b)[3],
+                                          typename Mfma<T>::v4 (&acc)[RT][3]) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int pi = t * 8 + pl;
+        const T aT = tl.v[side][0][k][pi], aP = tl.v[side][1][k][pi], aM = tl.v[side][2][k][pi];
+        acc[t][0] = Mfma<T>::run(aT, b[0], acc[t][0]);
+        acc[t][1] = Mfma<T>::run(aP, b[1], acc[t][1]);
+        acc[t][2] = Mfma<T>::run(aM, b[2], acc[t][2]);
+    }
+}
+
+template <typename T, int RT>
+__device__ __forceinline__ void syn_store(SynTile<T, RT>& tl, int j, int lane, bool odd, double lam, double pp,
+                                          double qq) {
+    const T a = (T)lam, b = (T)pp, c = (T)qq;
+    tl.v[0][0][j][lane] = a;
+    tl.v[0][1][j][lane] = b;
+    tl.v[0][2][j][lane] = c;
+    tl.v[1][0][j][lane] = odd ? -a : a;
+    tl.v[1][1][j][lane] = odd ? -c : c;
+    tl.v[1][2][j][lane] = odd ? -b : b;
+}
+
+template <typename T, int RT>
+__global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const double2* __restrict__ spin,
+                                                              double* __restrict__ phase) {
+    typedef typename Mfma<T>::v4 v4;
+    constexpr int PW = 8 * RT;                        // ring pairs per wave
+    __shared__ SynTile<T, RT> tile[kSynWaves][2];
+    const int m = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int pbase = (blockIdx.x * kSynWaves + wv) * PW;
+    const int rb = blockIdx.z * 8;
+    const int lmax = A.lmax;
+    const int64_t base = mbase(m, lmax);
+    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const int me = lane % PW;                         // the ring pair this lane recurses
+    const bool writer = lane < PW;
+
+    Rec s;
+    rec_init(s, A, m, pbase + me);
+    int lo = __builtin_amdgcn_readfirstlane(wave_min(s.ls));
+    int hi = __builtin_amdgcn_readfirstlane(wave_max(s.ls <= lmax ? s.ls : 0));
+    if (m < 2) hi = max(hi, 2);
+
+    v4 acc[RT][3];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) acc[t][f] = v4{0, 0, 0, 0};
+
+    const int row = lane & 15, k = lane >> 4;
+    const int side = row & 1, pl = row >> 1;
+    const int col = lane & 15, ri = col & 1;
+    const int rhs = rb + (col >> 1);
+    const bool rhs_ok = rhs < A.nrhs;
+    // padding columns read RHS 0 and are never stored
+    const double* __restrict__ sbase = reinterpret_cast<const double*>(spin) +
+                                       (((int64_t)(rhs_ok ? rhs : 0) * 3) * A.nalm + base) * 2 + ri;
+    auto load_b = [&](int l, double (&b)[3]) {
+        const int lc = min(l, lmax);              // beyond lmax the A operand is zero
+        b[0] = sbase[(int64_t)lc * 2];
+        b[1] = sbase[(A.nalm + lc) * 2];
+        b[2] = sbase[(2 * A.nalm + lc) * 2];
+    };
+    auto produce_any = [&](int l0, int q) {
+        for (int j = 0; j < 4; ++j) {
+            double lam, pp, qq;
+            rec_step(A, cf, m, l0 + j, lo, hi, s, lam, pp, qq);
+            if (writer) syn_store<T, RT>(tile[wv][q], j, lane, (l0 + j + m) & 1, lam, pp, qq);
+        }
+    };
+    auto produce_steady = [&](int l0, int q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            rec_next(cf, l0 + j, s);
+            if (writer) syn_store<T, RT>(tile[wv][q], j, lane, (l0 + j + m) & 1, s.l1, s.w1, s.q1);
+        }
+    };
+
+    if (lo <= lmax) {
+        produce_any(lo, 0);
+        double braw[3];
+        load_b(lo + k, braw);
+        wave_sync();
+        int q = 0, l0 = lo;
+        // rounds whose successor still needs activation or runs past lmax
+        for (; l0 <= lmax; l0 += 4, q ^= 1) {
+            const int ln = l0 + 4;
+            if (ln > hi && ln + 3 <= lmax) break;
+            T b[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+            load_b(ln + k, braw);
+            bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+            if (ln <= lmax) produce_any(ln, q ^ 1);
+            wave_sync();
+        }
+        // steady state: matrix products of this round, recursion of the next
+        for (; l0 + 7 <= lmax; l0 += 4, q ^= 1) {
+            T b[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+            load_b(l0 + 4 + k, braw);
+            bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+            produce_steady(l0 + 4, q ^ 1);
+            wave_sync();
+        }
+        // tail
+        for (; l0 <= lmax; l0 += 4, q ^= 1) {
+            const int ln = l0 + 4;
+            T b[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+            load_b(ln + k, braw);
+            bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+            if (ln <= lmax) produce_any(ln, q ^ 1);
+            wave_sync();
+        }
+    }
+
+    // epilogue: T directly; Q = (P + M)/2, U = (P - M)/(2i) with the
+    // re/im partner in the neighbouring lane
+    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = Mfma<T>::row(lane, v);
+            const int pair = pbase + t * 8 + (r >> 1), sd = r & 1;
+            const double Pv = (double)acc[t][1][v], Mv = (double)acc[t][2][v];
+            const double d = Pv - Mv;
+            const double dp = __shfl_xor(d, 1, 64);
+            if (pair < A.npairs && rhs_ok) {
+                double* o = phase + (((((int64_t)rhs * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 2 + sd) * 2 + ri;
+                o[0] = (double)acc[t][0][v];
+                o[fstride * 2] = 0.5 * (Pv + Mv);
+                o[fstride * 4] = ri ? -0.5 * dp : 0.5 * dp;
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// analysis: W waves x 32 ring pairs per block, rounds of 16 degrees, one
+// column tile of 8 RHS per block; the waves' products are summed in LDS
+// (FP64) and one partial-sum slot per block goes to the combine kernel
+// ---------------------------------------------------------------------------
+constexpr int kAnaPW = 32;                              // ring pairs per wave
+constexpr int kAnaKS = kAnaPW / 2;                      // K steps (2 pairs x 2 sides each)
+constexpr int kAnaRowLen = kAnaPW + 1;
+
+// sign flip by the sign bit: the mirror ring's operand is eps times the
+// north function, with eps fixed per lane for the whole kernel
+__device__ __forceinline__ float flip(float v, unsigned s) { return __uint_as_float(__float_as_uint(v) ^ s); }
+__device__ __forceinline__ double flip(double v, unsigned s) {
+    const unsigned long long b = __double_as_longlong(v) ^ ((unsigned long long)s << 32);
+    return __longlong_as_double(b);
+}
+
+template <typename T>
+__device__ __forceinline__ void bana_mfma(const T* tl, int oT, int oP, int oM, unsigned sgn,
+                                          const T (&bop)[kAnaKS][3], typename Mfma<T>::v4 (&C)[3]) {
+#pragma unroll
+    for (int st = 0; st < kAnaKS; ++st) {
+        const T aT = flip(tl[oT + 2 * st], sgn);
+        const T aP = flip(tl[oP + 2 * st], sgn);
+        const T aM = flip(tl[oM + 2 * st], sgn);
+        C[0] = Mfma<T>::run(aT, bop[st][0], C[0]);
+        C[1] = Mfma<T>::run(aP, bop[st][1], C[1]);
+        C[2] = Mfma<T>::run(aM, bop[st][2], C[2]);
+    }
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2* __restrict__ phase,
+                                                      const double* __restrict__ pair_w,
+                                                      double* __restrict__ partial) {
+    typedef typename Mfma<T>::v4 v4;
+    constexpr int kTile = 3 * 16 * kAnaRowLen;          // [f][j][pair], padded
+    static_assert(kTile >= 3 * 256, "tile too small for the partial products");
+    __shared__ T tile[W][2][kTile];
+    __shared__ int s_lo[W], s_hi[W];
+    const int m = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int pbase = (blockIdx.x * W + wv) * kAnaPW;
+    const int rb = blockIdx.z * 8;
+    const int lmax = A.lmax;
+    const int64_t base = mbase(m, lmax);
+    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
+    const int me = lane % kAnaPW;
+
+    Rec s;
+    rec_init(s, A, m, pbase + me);
+    int lo = wave_min(s.ls);
+    int hi = wave_max(s.ls <= lmax ? s.ls : 0);
+    if (lane == 0) { s_lo[wv] = lo; s_hi[wv] = hi; }
+
+    // B operands for every K step: pair = pbase + 2 st + k/2, side = k & 1,
+    // col = (rhs, re/im); weighted G^T, G^Q + i G^U, G^Q - i G^U
+    const int k = lane >> 4, col = lane & 15, ri = col & 1;
+    const int rhs = rb + (col >> 1);
+    const bool rhs_ok = rhs < A.nrhs;
+    T bop[kAnaKS][3];
+#pragma unroll
+    for (int st = 0; st < kAnaKS; ++st) {
+        const int pair = pbase + 2 * st + (k >> 1), sd = k & 1;
+        const bool ok = pair < A.npairs && rhs_ok;
+        const int pc = ok ? pair : 0;
+        const double w = pair_w[pc];
+        const double2* in = phase + ((((int64_t)(rhs_ok ? rhs : 0) * 3) * A.npairs + pc) * (A.mmax + 1) + m) * 2 + sd;
+        const double2 t0 = in[0], q0 = in[fstride], u0 = in[2 * fstride];
+        const double gt = ri ? t0.y : t0.x;
+        const double gp = ri ? (q0.y + u0.x) : (q0.x - u0.y);
+        const double gm = ri ? (q0.y - u0.x) : (q0.x + u0.y);
+        bop[st][0] = ok ? (T)(w * gt) : (T)0;
+        bop[st][1] = ok ? (T)(w * gp) : (T)0;
+        bop[st][2] = ok ? (T)(w * gm) : (T)0;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int q = 1; q < W; ++q) { lo = min(lo, s_lo[q]); hi = max(hi, s_hi[q]); }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    if (m < 2) hi = max(hi, 2);
+
+    const int nrhs = A.nrhs;
+    double* out = partial + ((int64_t)blockIdx.x * nrhs * 3) * A.nalm * 2;
+    const int ncol = min(8, nrhs - rb);
+    // degrees below the block's first active one: zero partial sums
+    {
+        const int lz = min(lo, lmax + 1);
+        const int total = (lz - m) * 3 * ncol * 2;
+        for (int q = threadIdx.x; q < total; q += 64 * W) {
+            const int c2 = q & 1, rr = (q >> 1) % ncol, f = ((q >> 1) / ncol) % 3, l = m + (q >> 1) / ncol / 3;
+            out[((((int64_t)(rb + rr)) * 3 + f) * A.nalm + base + l) * 2 + c2] = 0.0;
+        }
+    }
+
+    auto produce_any = [&](int l0, T* tl) {
+        for (int j = 0; j < 16; ++j) {
+            double lam, pp, qq;
+            rec_step(A, cf, m, l0 + j, lo, hi, s, lam, pp, qq);
+            if (lane < kAnaPW) {
+                tl[(0 * 16 + j) * kAnaRowLen + lane] = (T)lam;
+                tl[(1 * 16 + j) * kAnaRowLen + lane] = (T)pp;
+                tl[(2 * 16 + j) * kAnaRowLen + lane] = (T)qq;
+            }
+        }
+    };
+    auto produce_steady = [&](int l0, T* tl) {
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            rec_next(cf, l0 + j, s);
+            if (lane < kAnaPW) {
+                tl[(0 * 16 + j) * kAnaRowLen + lane] = (T)s.l1;
+                tl[(1 * 16 + j) * kAnaRowLen + lane] = (T)s.w1;
+                tl[(2 * 16 + j) * kAnaRowLen + lane] = (T)s.q1;
+            }
+        }
+    };
+
+    // A operand of this lane: degree row, pair 2 st + k/2, side k & 1; the
+    // mirror side reads eps (lam, q, p).  The degree parity of a row is the
+    // same in every round (rounds advance by 16 degrees).
+    const int row = lane & 15;
+    const int sd = k & 1;
+    const int pofs = row * kAnaRowLen + (k >> 1);
+    const int oT = pofs, oP = (sd ? 32 : 16) * kAnaRowLen + pofs, oM = (sd ? 16 : 32) * kAnaRowLen + pofs;
+    const unsigned sgn = (sd && ((lo + row + m) & 1)) ? 0x80000000u : 0u;
+
+    // one round: products of tile q, then (overlapped) the next round's
+    // recursion into tile q ^ 1, then the cross-wave sum of the products
+    auto finish = [&](int l0, int q, const v4 (&C)[3]) {
+        T* tl = tile[wv][q];
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tl[(f * 16 + Mfma<T>::row(lane, v)) * 16 + col] = C[f][v];
+        __syncthreads();
+        // sum over the waves in FP64 and write the block's slot
+        for (int e = threadIdx.x; e < 3 * 256; e += 64 * W) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w2 = 0; w2 < W; ++w2) sum += (double)tile[w2][q][e];
+            const int cc = e & 15, r = (e >> 4) & 15, f = e >> 8;
+            const int l = l0 + r, rr = rb + (cc >> 1);
+            if (l <= lmax && rr < nrhs)
+                out[(((int64_t)rr * 3 + f) * A.nalm + base + l) * 2 + (cc & 1)] = sum;
+        }
+        __syncthreads();
+    };
+
+    if (lo <= lmax) {
+        produce_any(lo, tile[wv][0]);
+        wave_sync();
+        int q = 0, l0 = lo;
+        for (; l0 <= lmax; l0 += 16, q ^= 1) {
+            const int ln = l0 + 16;
+            if (ln > hi && ln + 15 <= lmax) break;
+            v4 C[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+            bana_mfma<T>(tile[wv][q], oT, oP, oM, sgn, bop, C);
+            if (ln <= lmax) produce_any(ln, tile[wv][q ^ 1]);
+            wave_sync();
+            finish(l0, q, C);
+        }
+        for (; l0 + 31 <= lmax; l0 += 16, q ^= 1) {
+            v4 C[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+            bana_mfma<T>(tile[wv][q], oT, oP, oM, sgn, bop, C);
+            produce_steady(l0 + 16, tile[wv][q ^ 1]);
+            wave_sync();
+            finish(l0, q, C);
+        }
+        for (; l0 <= lmax; l0 += 16, q ^= 1) {
+            const int ln = l0 + 16;
+            v4 C[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+            bana_mfma<T>(tile[wv][q], oT, oP, oM, sgn, bop, C);
+            if (ln <= lmax) produce_any(ln, tile[wv][q ^ 1]);
+            wave_sync();
+            finish(l0, q, C);
+        }
+    }
+}
+
+BatchArgs batch_args(dm_plan* p, int nrhs) {
+    BatchArgs a;
+    a.lmax = p->lmax;
+    a.mmax = p->mmax;
+    a.npairs = p->npairs;
+    a.nrhs = nrhs;
+    a.nalm = p->nalm;
+    a.pair_x = p->d_pair_x;
+    a.coef = p->d_coef;
+    a.lstart = p->d_lstart;
+    a.seed = p->d_seed;
+    a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
+    return a;
+}
+
+constexpr int kAnaWaves = 8;
+
+}  // namespace
+
+// FP32 blocks hold 8 waves, FP64 blocks 4 (their LDS tiles are twice as big)
+static int bana_waves(dm_plan* p) { return p->precision == DM_MIXED ? kAnaWaves : kAnaWaves / 2; }
+
+int batched_analysis_slots(dm_plan* p) {
+    const int per = kAnaPW * bana_waves(p);
+    return (p->npairs + per - 1) / per;
+}
+
+hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
+    const BatchArgs A = batch_args(p, nrhs);
+    const int rt = p->precision == DM_MIXED ? 8 : 4;
+    dim3 grid((p->npairs + 8 * rt * kSynWaves - 1) / (8 * rt * kSynWaves), p->mmax + 1, (nrhs + 7) / 8);
+    dim3 block(64 * kSynWaves);
+    const double2* sp = reinterpret_cast<const double2*>(spin);
+    if (p->precision == DM_MIXED) hipLaunchKernelGGL((bsyn_kernel<float, 8>), grid, block, 0, s, A, sp, phase);
+    else hipLaunchKernelGGL((bsyn_kernel<double, 4>), grid, block, 0, s, A, sp, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_bana(dm_plan* p, int nrhs, const double* phase, const double* pair_w, double* partial,
+                       hipStream_t s) {
+    const BatchArgs A = batch_args(p, nrhs);
+    dim3 grid(batched_analysis_slots(p), p->mmax + 1, (nrhs + 7) / 8);
+    const double2* ph = reinterpret_cast<const double2*>(phase);
+    if (p->precision == DM_MIXED)
+        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves>), grid, dim3(64 * kAnaWaves), 0, s, A, ph, pair_w, partial);
+    else
+        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves / 2>), grid, dim3(32 * kAnaWaves), 0, s, A, ph, pair_w,
+                           partial);
+    return hipGetLastError();
+}
+
+}  // namespace dmwf
