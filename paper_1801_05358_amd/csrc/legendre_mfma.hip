@@ -18,6 +18,8 @@
 // col + 16 k).  T = double uses the FP64 matrix instruction; T = float
 // converts the functions and data to FP32 and accumulates in FP32 (the
 // mixed-precision path; the iterate itself stays FP64).
+#include <type_traits>
+
 #include "dmwf_internal.h"
 
 namespace dmwf {
@@ -147,9 +149,19 @@ __device__ __forceinline__ void rec_next(const double* __restrict__ cf, int l, R
 // ---------------------------------------------------------------------------
 constexpr int kSynWaves = 4;
 
+// [side][A_T, A_+2, A_-2][degree in round][pair], padded so that the 64
+// operand reads of one matrix instruction (2 sides x 4 degrees x 8 pairs)
+// fall in distinct LDS banks: degree rows 8 words apart modulo 32, sides 16
+// (FP32); FP64 values take two banks and are read 16 lanes at a time,
+// which needs the sides 8 doubles apart modulo 16
 template <typename T, int RT>
 struct SynTile {
-    T v[2][3][4][64];            // [side][A_T, A_+2, A_-2][degree in round][pair]
+    static constexpr int K = sizeof(T) == 4 ? 8 * RT + 8 : 8 * RT;
+    static constexpr int F = 4 * K;
+    static constexpr int S = sizeof(T) == 4 ? 3 * F + 16 : 3 * F + 8;
+    T v[2 * S];
+    __device__ T& at(int side, int f, int j, int pair) { return v[side * S + f * F + j * K + pair]; }
+    __device__ const T& at(int side, int f, int j, int pair) const { return v[side * S + f * F + j * K + pair]; }
 };
 
 template <typename T, int RT>
@@ -158,7 +170,7 @@ __device__ __forceinline__ void bsyn_mfma(const SynTile<T, RT>& tl, int k, int p
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int pi = t * 8 + pl;
-        const T aT = tl.v[side][0][k][pi], aP = tl.v[side][1][k][pi], aM = tl.v[side][2][k][pi];
+        const T aT = tl.at(side, 0, k, pi), aP = tl.at(side, 1, k, pi), aM = tl.at(side, 2, k, pi);
         acc[t][0] = Mfma<T>::run(aT, b[0], acc[t][0]);
         acc[t][1] = Mfma<T>::run(aP, b[1], acc[t][1]);
         acc[t][2] = Mfma<T>::run(aM, b[2], acc[t][2]);
@@ -169,12 +181,12 @@ template <typename T, int RT>
 __device__ __forceinline__ void syn_store(SynTile<T, RT>& tl, int j, int lane, bool odd, double lam, double pp,
                                           double qq) {
     const T a = (T)lam, b = (T)pp, c = (T)qq;
-    tl.v[0][0][j][lane] = a;
-    tl.v[0][1][j][lane] = b;
-    tl.v[0][2][j][lane] = c;
-    tl.v[1][0][j][lane] = odd ? -a : a;
-    tl.v[1][1][j][lane] = odd ? -c : c;
-    tl.v[1][2][j][lane] = odd ? -b : b;
+    tl.at(0, 0, j, lane) = a;
+    tl.at(0, 1, j, lane) = b;
+    tl.at(0, 2, j, lane) = c;
+    tl.at(1, 0, j, lane) = odd ? -a : a;
+    tl.at(1, 1, j, lane) = odd ? -c : c;
+    tl.at(1, 2, j, lane) = odd ? -b : b;
 }
 
 template <typename T, int RT>
@@ -190,8 +202,9 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefStride;
-    const int me = lane % PW;                         // the ring pair this lane recurses
-    const bool writer = lane < PW;
+    // the ring pair this lane recurses; with PW < 64 the upper lanes repeat
+    // the lower ones and store the same values to the same addresses
+    const int me = lane % PW;
 
     Rec s;
     rec_init(s, A, m, pbase + me);
@@ -223,14 +236,14 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         for (int j = 0; j < 4; ++j) {
             double lam, pp, qq;
             rec_step(A, cf, m, l0 + j, lo, hi, s, lam, pp, qq);
-            if (writer) syn_store<T, RT>(tile[wv][q], j, lane, (l0 + j + m) & 1, lam, pp, qq);
+            syn_store<T, RT>(tile[wv][q], j, me, (l0 + j + m) & 1, lam, pp, qq);
         }
     };
     auto produce_steady = [&](int l0, int q) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             rec_next(cf, l0 + j, s);
-            if (writer) syn_store<T, RT>(tile[wv][q], j, lane, (l0 + j + m) & 1, s.l1, s.w1, s.q1);
+            syn_store<T, RT>(tile[wv][q], j, me, (l0 + j + m) & 1, s.l1, s.w1, s.q1);
         }
     };
 
@@ -275,56 +288,83 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         }
     }
 
-    // epilogue: T directly; Q = (P + M)/2, U = (P - M)/(2i) with the
-    // re/im partner in the neighbouring lane
-    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
+    // epilogue, through the wave's (now free) tile: per 8 ring pairs the
+    // raw products go to LDS as [f][pair][rhs][side][re/im]; then each lane
+    // takes one (pair, rhs), forms T, Q = (P + M)/2, U = (P - M)/(2i) and
+    // writes 32 contiguous bytes (both sides, re/im) per field
+    double* stg = reinterpret_cast<double*>(&tile[wv][0]);
+    static_assert(sizeof(SynTile<T, RT>) * 2 >= 3 * 8 * 8 * 4 * sizeof(double), "staging does not fit");
+    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 4;     // doubles per field
+    const int pl_r = lane >> 3, rc_r = lane & 7;
+    const int rhs_w = rb + rc_r;
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+    for (int t = 0; t < RT; ++t) {
+        wave_sync();
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = Mfma<T>::row(lane, v);
-            const int pair = pbase + t * 8 + (r >> 1), sd = r & 1;
-            const double Pv = (double)acc[t][1][v], Mv = (double)acc[t][2][v];
-            const double d = Pv - Mv;
-            const double dp = __shfl_xor(d, 1, 64);
-            if (pair < A.npairs && rhs_ok) {
-                double* o = phase + (((((int64_t)rhs * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 2 + sd) * 2 + ri;
-                o[0] = (double)acc[t][0][v];
-                o[fstride * 2] = 0.5 * (Pv + Mv);
-                o[fstride * 4] = ri ? -0.5 * dp : 0.5 * dp;
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = Mfma<T>::row(lane, v);
+                stg[((f * 8 + (r >> 1)) * 8 + (col >> 1)) * 4 + (r & 1) * 2 + ri] = (double)acc[t][f][v];
             }
-        }
-}
-
-// ---------------------------------------------------------------------------
-// analysis: W waves x 32 ring pairs per block, rounds of 16 degrees, one
-// column tile of 8 RHS per block; the waves' products are summed in LDS
-// (FP64) and one partial-sum slot per block goes to the combine kernel
-// ---------------------------------------------------------------------------
-constexpr int kAnaPW = 32;                              // ring pairs per wave
-constexpr int kAnaKS = kAnaPW / 2;                      // K steps (2 pairs x 2 sides each)
-constexpr int kAnaRowLen = kAnaPW + 1;
-
-// sign flip by the sign bit: the mirror ring's operand is eps times the
-// north function, with eps fixed per lane for the whole kernel
-__device__ __forceinline__ float flip(float v, unsigned s) { return __uint_as_float(__float_as_uint(v) ^ s); }
-__device__ __forceinline__ double flip(double v, unsigned s) {
-    const unsigned long long b = __double_as_longlong(v) ^ ((unsigned long long)s << 32);
-    return __longlong_as_double(b);
-}
-
-template <typename T>
-__device__ __forceinline__ void bana_mfma(const T* tl, int oT, int oP, int oM, unsigned sgn,
-                                          const T (&bop)[kAnaKS][3], typename Mfma<T>::v4 (&C)[3]) {
+        wave_sync();
+        const int pair = pbase + t * 8 + pl_r;
+        if (pair < A.npairs && rhs_w < A.nrhs) {
+            const double* g = stg + (pl_r * 8 + rc_r) * 4;
+            const double2 tn = {g[0], g[1]}, ts = {g[2], g[3]};
+            const double* gp = g + 8 * 8 * 4;
+            const double* gm = g + 2 * 8 * 8 * 4;
+            double qv[4], uv[4];
 #pragma unroll
-    for (int st = 0; st < kAnaKS; ++st) {
-        const T aT = flip(tl[oT + 2 * st], sgn);
-        const T aP = flip(tl[oP + 2 * st], sgn);
-        const T aM = flip(tl[oM + 2 * st], sgn);
-        C[0] = Mfma<T>::run(aT, bop[st][0], C[0]);
-        C[1] = Mfma<T>::run(aP, bop[st][1], C[1]);
-        C[2] = Mfma<T>::run(aM, bop[st][2], C[2]);
+            for (int sd = 0; sd < 2; ++sd) {
+                const double pr = gp[2 * sd], pi = gp[2 * sd + 1], mr = gm[2 * sd], mi = gm[2 * sd + 1];
+                qv[2 * sd] = 0.5 * (pr + mr);
+                qv[2 * sd + 1] = 0.5 * (pi + mi);
+                uv[2 * sd] = 0.5 * (pi - mi);
+                uv[2 * sd + 1] = -0.5 * (pr - mr);
+            }
+            double2* o = reinterpret_cast<double2*>(
+                phase + ((((int64_t)rhs_w * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 4);
+            o[0] = tn;
+            o[1] = ts;
+            double2* oq = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + fstride);
+            oq[0] = double2{qv[0], qv[1]};
+            oq[1] = double2{qv[2], qv[3]};
+            double2* ou = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + 2 * fstride);
+            ou[0] = double2{uv[0], uv[1]};
+            ou[1] = double2{uv[2], uv[3]};
+        }
     }
+}
+
+// ---------------------------------------------------------------------------
+// analysis: W waves x 64 ring pairs per block (one pair per lane), rounds of
+// 16 degrees, one column tile of 8 RHS per block.  The K dimension is split
+// by side: the north rings give C_N = sum A_N G_N, the mirror rings
+// C_S = sum A_S G_S with A_S = (lam, q, p) unsigned, and a round's output
+// row l is C_N + eps_l C_S.  Each wave's tile holds one round: the matrix
+// products read it, then the recursion overwrites it with the next round.
+// The waves' outputs are summed in LDS (FP64) one round late, and one
+// partial-sum slot per block goes to the combine kernel.
+// ---------------------------------------------------------------------------
+constexpr int kAnaPW = 64;                              // ring pairs per wave
+constexpr int kAnaKH = kAnaPW / 4;                      // K steps per side
+constexpr int kAnaKS = 2 * kAnaKH;                      // K steps per round
+// tile row length: the operand reads of one matrix instruction (16 degrees
+// x 4 pairs) are conflict-free with rows 2 words apart modulo 32 (FP32,
+// 32 lanes at a time) or 1 double apart modulo 16 (FP64, 16 lanes at a time)
+template <typename T>
+constexpr int ana_rl() { return sizeof(T) == 4 ? kAnaPW + 2 : kAnaPW + 1; }
+template <typename T>
+constexpr int ana_tile() { return 3 * 16 * ana_rl<T>(); }       // [f][degree][pair]
+constexpr int kRedCol = 17;                             // [f][col][row] with padded columns
+constexpr int kRedF = 16 * kRedCol;
+
+// recursion of an activation round: every lane advances (lanes before
+// their start degree hold zeros), lanes whose start degree is l take seeds
+__device__ __forceinline__ void rec_act(const BatchArgs& A, const double* __restrict__ cf, int m, int l, Rec& s) {
+    rec_advance(cf + (int64_t)l * kCoefStride, s);
+    rec_activate(A, m, l, s);
 }
 
 template <typename T, int W>
@@ -332,9 +372,9 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
                                                       const double* __restrict__ pair_w,
                                                       double* __restrict__ partial) {
     typedef typename Mfma<T>::v4 v4;
-    constexpr int kTile = 3 * 16 * kAnaRowLen;          // [f][j][pair], padded
-    static_assert(kTile >= 3 * 256, "tile too small for the partial products");
-    __shared__ T tile[W][2][kTile];
+    constexpr int RL = ana_rl<T>();
+    __shared__ T tile[W][ana_tile<T>()];
+    __shared__ T red[2][W][3 * kRedF];
     __shared__ int s_lo[W], s_hi[W];
     const int m = blockIdx.y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -344,23 +384,24 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefStride;
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
-    const int me = lane % kAnaPW;
 
     Rec s;
-    rec_init(s, A, m, pbase + me);
+    rec_init(s, A, m, pbase + lane);
     int lo = wave_min(s.ls);
     int hi = wave_max(s.ls <= lmax ? s.ls : 0);
     if (lane == 0) { s_lo[wv] = lo; s_hi[wv] = hi; }
 
-    // B operands for every K step: pair = pbase + 2 st + k/2, side = k & 1,
-    // col = (rhs, re/im); weighted G^T, G^Q + i G^U, G^Q - i G^U
+    // B operands: K step st < KH takes the north ring of pair 4 st + k,
+    // st >= KH the mirror ring of pair 4 (st - KH) + k; col = (rhs, re/im);
+    // weighted G^T, G^Q + i G^U, G^Q - i G^U
     const int k = lane >> 4, col = lane & 15, ri = col & 1;
     const int rhs = rb + (col >> 1);
     const bool rhs_ok = rhs < A.nrhs;
     T bop[kAnaKS][3];
 #pragma unroll
     for (int st = 0; st < kAnaKS; ++st) {
-        const int pair = pbase + 2 * st + (k >> 1), sd = k & 1;
+        const int sd = st / kAnaKH;
+        const int pair = pbase + 4 * (st % kAnaKH) + k;
         const bool ok = pair < A.npairs && rhs_ok;
         const int pc = ok ? pair : 0;
         const double w = pair_w[pc];
@@ -385,98 +426,108 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
     double* out = partial + ((int64_t)blockIdx.x * nrhs * 3) * A.nalm * 2;
     const int ncol = min(8, nrhs - rb);
     // degrees below the block's first active one: zero partial sums
+    // (consecutive threads write consecutive (l, re/im))
     {
-        const int lz = min(lo, lmax + 1);
-        const int total = (lz - m) * 3 * ncol * 2;
+        const int nl = min(lo, lmax + 1) - m;
+        const int run = 2 * nl, total = run * 3 * ncol;
         for (int q = threadIdx.x; q < total; q += 64 * W) {
-            const int c2 = q & 1, rr = (q >> 1) % ncol, f = ((q >> 1) / ncol) % 3, l = m + (q >> 1) / ncol / 3;
-            out[((((int64_t)(rb + rr)) * 3 + f) * A.nalm + base + l) * 2 + c2] = 0.0;
+            const int fr = q / run, w = q - fr * run;           // fr = rhs * 3 + f within the tile
+            out[((int64_t)(rb * 3 + fr) * A.nalm + base + m) * 2 + w] = 0.0;
         }
     }
+    if (lo > lmax) return;
 
-    auto produce_any = [&](int l0, T* tl) {
-        for (int j = 0; j < 16; ++j) {
-            double lam, pp, qq;
-            rec_step(A, cf, m, l0 + j, lo, hi, s, lam, pp, qq);
-            if (lane < kAnaPW) {
-                tl[(0 * 16 + j) * kAnaRowLen + lane] = (T)lam;
-                tl[(1 * 16 + j) * kAnaRowLen + lane] = (T)pp;
-                tl[(2 * 16 + j) * kAnaRowLen + lane] = (T)qq;
+    T* tl = tile[wv];
+    auto store = [&](int j, double lam, double pp, double qq) {
+        tl[(0 * 16 + j) * RL + lane] = (T)lam;
+        tl[(1 * 16 + j) * RL + lane] = (T)pp;
+        tl[(2 * 16 + j) * RL + lane] = (T)qq;
+    };
+    // recursion of the round starting at degree l0 into the tile
+    auto produce = [&](int l0, auto mode) {
+        constexpr int kMode = decltype(mode)::value;            // 0 steady, 1 activation, 2 past lmax
+        if constexpr (kMode == 2) {
+            for (int j = 0; j < 16; ++j) {
+                double lam, pp, qq;
+                rec_step(A, cf, m, l0 + j, lo, hi, s, lam, pp, qq);
+                store(j, lam, pp, qq);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if constexpr (kMode == 1) rec_act(A, cf, m, l0 + j, s);
+                else rec_next(cf, l0 + j, s);
+                store(j, s.l1, s.w1, s.q1);
             }
         }
     };
-    auto produce_steady = [&](int l0, T* tl) {
-#pragma unroll 4
-        for (int j = 0; j < 16; ++j) {
-            rec_next(cf, l0 + j, s);
-            if (lane < kAnaPW) {
-                tl[(0 * 16 + j) * kAnaRowLen + lane] = (T)s.l1;
-                tl[(1 * 16 + j) * kAnaRowLen + lane] = (T)s.w1;
-                tl[(2 * 16 + j) * kAnaRowLen + lane] = (T)s.q1;
-            }
-        }
-    };
 
-    // A operand of this lane: degree row, pair 2 st + k/2, side k & 1; the
-    // mirror side reads eps (lam, q, p).  The degree parity of a row is the
-    // same in every round (rounds advance by 16 degrees).
+    // A operand of this lane: degree row, pair 4 (st % KH) + k; the mirror
+    // half reads (lam, q, p)
     const int row = lane & 15;
-    const int sd = k & 1;
-    const int pofs = row * kAnaRowLen + (k >> 1);
-    const int oT = pofs, oP = (sd ? 32 : 16) * kAnaRowLen + pofs, oM = (sd ? 16 : 32) * kAnaRowLen + pofs;
-    const unsigned sgn = (sd && ((lo + row + m) & 1)) ? 0x80000000u : 0u;
+    const int pofs = row * RL + k;
+    const int oN[3] = {pofs, 16 * RL + pofs, 32 * RL + pofs};
+    const int oS[3] = {pofs, 32 * RL + pofs, 16 * RL + pofs};
+    // eps of each output element: rounds advance by 16 degrees, so the
+    // parity of a row is the same in every round
+    T sg[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sg[v] = ((lo + Mfma<T>::row(lane, v) + m) & 1) ? (T)-1 : (T)1;
 
-    // one round: products of tile q, then (overlapped) the next round's
-    // recursion into tile q ^ 1, then the cross-wave sum of the products
-    auto finish = [&](int l0, int q, const v4 (&C)[3]) {
-        T* tl = tile[wv][q];
+    // sum over the waves (FP64) of the round that started at degree l0,
+    // held in red[qb], into the block's slot; thread t takes re/im t & 1,
+    // degree (t >> 1) & 15 and (rhs, f) t >> 5, so that each run of 32
+    // threads writes 256 contiguous bytes
+    auto reduce = [&](int l0, int qb) {
+        for (int e = threadIdx.x; e < 3 * 256; e += 64 * W) {
+            const int ri2 = e & 1, r = (e >> 1) & 15, fr = e >> 5;
+            const int rr = fr / 3, f = fr - 3 * rr;
+            const int ofs = f * kRedF + (2 * rr + ri2) * kRedCol + r;
+            double sum = 0.0;
+#pragma unroll
+            for (int w2 = 0; w2 < W; ++w2) sum += (double)red[qb][w2][ofs];
+            const int l = l0 + r;
+            if (l <= lmax && rb + rr < nrhs)
+                out[((int64_t)((rb + rr) * 3 + f) * A.nalm + base + l) * 2 + ri2] = sum;
+        }
+    };
+
+    if (lo + 15 <= lmax) produce(lo, std::integral_constant<int, 1>());
+    else produce(lo, std::integral_constant<int, 2>());
+    wave_sync();
+    int q = 0, l0 = lo;
+    auto round = [&](auto mode) {
+        v4 CN[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+        v4 CS[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+#pragma unroll
+        for (int st = 0; st < kAnaKS; ++st) {
+            const int* o = st < kAnaKH ? oN : oS;
+            const int po = 4 * (st % kAnaKH);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                v4& C = st < kAnaKH ? CN[f] : CS[f];
+                C = Mfma<T>::run(tl[o[f] + po], bop[st][f], C);
+            }
+            // keep the operand loads within a few K steps of their use
+            if (st % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        // the products have read the tile (LDS operations of a wave
+        // complete in order): the next round's recursion overwrites it
+        if (l0 + 16 <= lmax) produce(l0 + 16, mode);
+        if (l0 > lo) reduce(l0 - 16, q ^ 1);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) tl[(f * 16 + Mfma<T>::row(lane, v)) * 16 + col] = C[f][v];
-        __syncthreads();
-        // sum over the waves in FP64 and write the block's slot
-        for (int e = threadIdx.x; e < 3 * 256; e += 64 * W) {
-            double sum = 0.0;
-#pragma unroll
-            for (int w2 = 0; w2 < W; ++w2) sum += (double)tile[w2][q][e];
-            const int cc = e & 15, r = (e >> 4) & 15, f = e >> 8;
-            const int l = l0 + r, rr = rb + (cc >> 1);
-            if (l <= lmax && rr < nrhs)
-                out[(((int64_t)rr * 3 + f) * A.nalm + base + l) * 2 + (cc & 1)] = sum;
-        }
+            for (int v = 0; v < 4; ++v)
+                red[q][wv][f * kRedF + col * kRedCol + Mfma<T>::row(lane, v)] = CN[f][v] + sg[v] * CS[f][v];
         __syncthreads();
     };
-
-    if (lo <= lmax) {
-        produce_any(lo, tile[wv][0]);
-        wave_sync();
-        int q = 0, l0 = lo;
-        for (; l0 <= lmax; l0 += 16, q ^= 1) {
-            const int ln = l0 + 16;
-            if (ln > hi && ln + 15 <= lmax) break;
-            v4 C[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
-            bana_mfma<T>(tile[wv][q], oT, oP, oM, sgn, bop, C);
-            if (ln <= lmax) produce_any(ln, tile[wv][q ^ 1]);
-            wave_sync();
-            finish(l0, q, C);
-        }
-        for (; l0 + 31 <= lmax; l0 += 16, q ^= 1) {
-            v4 C[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
-            bana_mfma<T>(tile[wv][q], oT, oP, oM, sgn, bop, C);
-            produce_steady(l0 + 16, tile[wv][q ^ 1]);
-            wave_sync();
-            finish(l0, q, C);
-        }
-        for (; l0 <= lmax; l0 += 16, q ^= 1) {
-            const int ln = l0 + 16;
-            v4 C[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
-            bana_mfma<T>(tile[wv][q], oT, oP, oM, sgn, bop, C);
-            if (ln <= lmax) produce_any(ln, tile[wv][q ^ 1]);
-            wave_sync();
-            finish(l0, q, C);
-        }
-    }
+    // rounds whose successor has lanes starting in it
+    for (; l0 + 16 <= hi && l0 + 31 <= lmax; l0 += 16, q ^= 1) round(std::integral_constant<int, 1>());
+    for (; l0 + 31 <= lmax; l0 += 16, q ^= 1) round(std::integral_constant<int, 0>());
+    for (; l0 <= lmax; l0 += 16, q ^= 1) round(std::integral_constant<int, 2>());
+    // the last round's sum
+    reduce(l0 - 16, q ^ 1);
 }
 
 BatchArgs batch_args(dm_plan* p, int nrhs) {
