@@ -50,42 +50,80 @@ __device__ __forceinline__ double2 phase_rot(int m, int den) {
     return make_double2(c, s);
 }
 
+// Radix-2 stages in passes of up to three: one pass loads the 2^R elements
+// base + c h (h = 2^s, c < 2^R) that stages s .. s+R-1 combine, applies the
+// R stages in registers and stores them back, so that the LDS round trips
+// and barriers drop threefold.  The stage-(s+t) twiddle of element c is
+// W(j, s+t+1) w_t(c mod 2^t), with W(x, S) = exp(-2 pi i x / 2^S),
+// j = base mod h and w_t(r) = exp(-2 pi i r / 2^(t+1)) a root of unity of
+// order <= 8, so each group loads only R twiddles.
+__device__ __forceinline__ double2 root_mul(double2 w, int r, int t, bool inv) {
+    // w * exp(-+ 2 pi i r / 2^(t+1)), r < 2^t, t <= 2
+    if (r == 0) return w;
+    const double sg = inv ? -1.0 : 1.0;
+    if (t == 1 || r == 2) return make_double2(sg * w.y, -sg * w.x);            // * (-+i)
+    const double c = 0.70710678118654752440;                                  // r = 1 or 3, t = 2
+    const double2 z = r == 1 ? make_double2(c, -sg * c) : make_double2(-c, -sg * c);
+    return cmul(w, z);
+}
+
+template <int R, bool DIT>
+__device__ __forceinline__ void fft_pass(double2* buf, int M, int s, int logMmax, const double2* __restrict__ tw,
+                                         bool inv) {
+    constexpr int G = 1 << R;
+    const int h = 1 << s;
+    const int ngroups = M >> R;
+    for (int q = threadIdx.x; q < ngroups; q += blockDim.x) {
+        const int j = q & (h - 1);
+        const int base = ((q >> s) << (s + R)) + j;
+        double2 x[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) x[c] = buf[base + c * h];
+        double2 wb[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            wb[t] = tw[j << (logMmax - s - t - 1)];
+            if (inv) wb[t].y = -wb[t].y;
+        }
+#pragma unroll
+        for (int tt = 0; tt < R; ++tt) {
+            const int t = DIT ? tt : R - 1 - tt;
+            const int half = 1 << t;
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                if (c & half) continue;
+                const double2 w = root_mul(wb[t], c & (half - 1), t, inv);
+                const double2 a = x[c], b = x[c + half];
+                if (DIT) {
+                    const double2 bw = cmul(b, w);
+                    x[c] = make_double2(a.x + bw.x, a.y + bw.y);
+                    x[c + half] = make_double2(a.x - bw.x, a.y - bw.y);
+                } else {
+                    x[c] = make_double2(a.x + b.x, a.y + b.y);
+                    x[c + half] = cmul(make_double2(a.x - b.x, a.y - b.y), w);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < G; ++c) buf[base + c * h] = x[c];
+    }
+    __syncthreads();
+}
+
 // decimation in time: bit-reversed input, natural output
 __device__ void fft_dit(double2* buf, int M, int logM, int logMmax, const double2* __restrict__ tw, bool inv) {
-    const int nt = blockDim.x;
-    for (int s = 0; s < logM; ++s) {
-        const int h = 1 << s;
-        for (int q = threadIdx.x; q < M / 2; q += nt) {
-            const int g = q >> s, j = q & (h - 1);
-            const int i0 = (g << (s + 1)) + j, i1 = i0 + h;
-            double2 w = tw[j << (logMmax - s - 1)];
-            if (inv) w.y = -w.y;
-            const double2 a = buf[i0];
-            const double2 b = cmul(buf[i1], w);
-            buf[i0] = make_double2(a.x + b.x, a.y + b.y);
-            buf[i1] = make_double2(a.x - b.x, a.y - b.y);
-        }
-        __syncthreads();
-    }
+    int s = 0;
+    for (; s + 3 <= logM; s += 3) fft_pass<3, true>(buf, M, s, logMmax, tw, inv);
+    if (logM - s == 2) fft_pass<2, true>(buf, M, s, logMmax, tw, inv);
+    else if (logM - s == 1) fft_pass<1, true>(buf, M, s, logMmax, tw, inv);
 }
 
 // decimation in frequency: natural input, bit-reversed output
 __device__ void fft_dif(double2* buf, int M, int logM, int logMmax, const double2* __restrict__ tw, bool inv) {
-    const int nt = blockDim.x;
-    for (int s = logM - 1; s >= 0; --s) {
-        const int h = 1 << s;
-        for (int q = threadIdx.x; q < M / 2; q += nt) {
-            const int g = q >> s, j = q & (h - 1);
-            const int i0 = (g << (s + 1)) + j, i1 = i0 + h;
-            double2 w = tw[j << (logMmax - s - 1)];
-            if (inv) w.y = -w.y;
-            const double2 a = buf[i0];
-            const double2 b = buf[i1];
-            buf[i0] = make_double2(a.x + b.x, a.y + b.y);
-            buf[i1] = cmul(make_double2(a.x - b.x, a.y - b.y), w);
-        }
-        __syncthreads();
-    }
+    int top = logM;
+    for (; top >= 3; top -= 3) fft_pass<3, false>(buf, M, top - 3, logMmax, tw, inv);
+    if (top == 2) fft_pass<2, false>(buf, M, 0, logMmax, tw, inv);
+    else if (top == 1) fft_pass<1, false>(buf, M, 0, logMmax, tw, inv);
 }
 
 // Forward DFT core.  On entry buf[brev(j)] holds a_j (times chirp_j for
