@@ -82,15 +82,45 @@ struct Rec {
     int ls, pr;
 };
 
-__device__ __forceinline__ void rec_advance(const double* __restrict__ c, Rec& s) {
-    const double ax = c[0] * s.x, bx = c[2] * s.x;
-    const double nl = ax * s.l1 - c[1] * s.l0;
-    const double nw = (bx + c[3]) * s.w1 - c[4] * s.w0;
-    const double nq = (bx - c[3]) * s.q1 - c[4] * s.q0;
+// recursion coefficients of one degree: spin 0 (A, B), spin 2 (alpha,
+// alpha beta, gamma)
+struct Coef {
+    double a, b, al, ab, ga;
+};
+
+__device__ __forceinline__ Coef coef_at(const double* __restrict__ c) { return Coef{c[0], c[1], c[2], c[3], c[4]}; }
+
+__device__ __forceinline__ void rec_advance(const Coef& c, Rec& s) {
+    const double ax = c.a * s.x, bx = c.al * s.x;
+    const double nl = ax * s.l1 - c.b * s.l0;
+    const double nw = (bx + c.ab) * s.w1 - c.ga * s.w0;
+    const double nq = (bx - c.ab) * s.q1 - c.ga * s.q0;
     s.l0 = s.l1; s.l1 = nl;
     s.w0 = s.w1; s.w1 = nw;
     s.q0 = s.q1; s.q1 = nq;
 }
+
+__device__ __forceinline__ void rec_advance(const double* __restrict__ c, Rec& s) { rec_advance(coef_at(c), s); }
+
+// The recursion coefficients reach the steady loops through LDS rather than
+// scalar loads: scalar and LDS loads share one wait counter and scalar loads
+// return out of order, so every wait for an LDS operand would also wait for
+// the coefficient loads.  A group of G degrees (5 coefficients each) is
+// loaded one round ahead by lane t < 5G (one double each, vector loads),
+// stored to LDS in the following round and read as broadcasts in the round
+// after.  Every lane loads and stores (lanes >= 5G repeat the last value
+// into their own slot), so the loop body has no branch and the wait for the
+// load stays precise; degrees past lmax are clamped to lmax (a group past
+// lmax is loaded but never used).
+constexpr int kCoefN = 5;
+
+__device__ __forceinline__ double coef_fetch(const double* __restrict__ cf, int l0, int lmax, int t, int G) {
+    const int tc = min(t, G * kCoefN - 1);
+    const int d = tc / kCoefN, i = tc - d * kCoefN;
+    return cf[(int64_t)min(l0 + d, lmax) * kCoefStride + i];
+}
+
+__device__ __forceinline__ Coef coef_lds(const double* c) { return Coef{c[0], c[1], c[2], c[3], c[4]}; }
 
 __device__ __forceinline__ void rec_activate(const BatchArgs& A, int m, int l, Rec& s) {
     const int64_t o = (int64_t)m * A.npairs + s.pr;
@@ -195,6 +225,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     typedef typename Mfma<T>::v4 v4;
     constexpr int PW = 8 * RT;                        // ring pairs per wave
     __shared__ SynTile<T, RT> tile[kSynWaves][2];
+    __shared__ double cofw[kSynWaves][2][64];
     const int m = blockIdx.y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int pbase = (blockIdx.x * kSynWaves + wv) * PW;
@@ -239,13 +270,6 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
             syn_store<T, RT>(tile[wv][q], j, me, (l0 + j + m) & 1, lam, pp, qq);
         }
     };
-    auto produce_steady = [&](int l0, int q) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            rec_next(cf, l0 + j, s);
-            syn_store<T, RT>(tile[wv][q], j, me, (l0 + j + m) & 1, s.l1, s.w1, s.q1);
-        }
-    };
 
     if (lo <= lmax) {
         produce_any(lo, 0);
@@ -266,14 +290,30 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
             wave_sync();
         }
         // steady state: matrix products of this round, recursion of the next
-        for (; l0 + 7 <= lmax; l0 += 4, q ^= 1) {
-            T b[3];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
-            load_b(l0 + 4 + k, braw);
-            bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
-            produce_steady(l0 + 4, q ^ 1);
+        if (l0 + 7 <= lmax) {
+            // coefficients of the first steady recursion (degrees l0 + 4 ..
+            // l0 + 7) to LDS slot 0, the next group in flight
+            cofw[wv][0][lane] = coef_fetch(cf, l0 + 4, lmax, lane, 4);
+            double creg = coef_fetch(cf, l0 + 8, lmax, lane, 4);
             wave_sync();
+            int cs = 0;
+            for (; l0 + 7 <= lmax; l0 += 4, q ^= 1, cs ^= 1) {
+                T b[3];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+                // the in-flight group (degrees l0 + 8 ..) to the other slot,
+                // then the group after it, then the next B operands
+                cofw[wv][cs ^ 1][lane] = creg;
+                creg = coef_fetch(cf, l0 + 12, lmax, lane, 4);
+                load_b(l0 + 4 + k, braw);
+                bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    rec_advance(coef_lds(&cofw[wv][cs][j * kCoefN]), s);
+                    syn_store<T, RT>(tile[wv][q ^ 1], j, me, (l0 + 4 + j + m) & 1, s.l1, s.w1, s.q1);
+                }
+                wave_sync();
+            }
         }
         // tail
         for (; l0 <= lmax; l0 += 4, q ^= 1) {
@@ -375,6 +415,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
     constexpr int RL = ana_rl<T>();
     __shared__ T tile[W][ana_tile<T>()];
     __shared__ T red[2][W][3 * kRedF];
+    __shared__ double cofb[2][128];                     // recursion coefficients of 16 degrees
     __shared__ int s_lo[W], s_hi[W];
     const int m = blockIdx.y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -443,8 +484,9 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
         tl[(1 * 16 + j) * RL + lane] = (T)pp;
         tl[(2 * 16 + j) * RL + lane] = (T)qq;
     };
-    // recursion of the round starting at degree l0 into the tile
-    auto produce = [&](int l0, auto mode) {
+    // recursion of the round starting at degree l0 into the tile; modes 0
+    // (steady) and 1 (activation) take the coefficients from cofb[cq]
+    auto produce = [&](int l0, int cq, auto mode) {
         constexpr int kMode = decltype(mode)::value;            // 0 steady, 1 activation, 2 past lmax
         if constexpr (kMode == 2) {
             for (int j = 0; j < 16; ++j) {
@@ -455,12 +497,19 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
         } else {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                if constexpr (kMode == 1) rec_act(A, cf, m, l0 + j, s);
-                else rec_next(cf, l0 + j, s);
+                rec_advance(coef_lds(&cofb[cq][j * kCoefN]), s);
+                if constexpr (kMode == 1) rec_activate(A, m, l0 + j, s);
                 store(j, s.l1, s.w1, s.q1);
             }
         }
     };
+    // coefficient pipeline (wave 0): cofb[cq] holds the degrees the current
+    // round's recursion needs, creg the 16 degrees after them
+    auto coef_group = [&](int l, int slot) {
+        cofb[slot][lane] = coef_fetch(cf, l, lmax, lane, 16);
+        cofb[slot][lane + 64] = coef_fetch(cf, l, lmax, lane + 64, 16);
+    };
+    double creg0 = 0.0, creg1 = 0.0;
 
     // A operand of this lane: degree row, pair 4 (st % KH) + k; the mirror
     // half reads (lam, q, p)
@@ -492,9 +541,20 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
         }
     };
 
-    if (lo + 15 <= lmax) produce(lo, std::integral_constant<int, 1>());
-    else produce(lo, std::integral_constant<int, 2>());
-    wave_sync();
+    if (lo + 15 <= lmax) {
+        for (int j = 0; j < 16; ++j) {
+            rec_act(A, cf, m, lo + j, s);
+            store(j, s.l1, s.w1, s.q1);
+        }
+    } else {
+        produce(lo, 0, std::integral_constant<int, 2>());
+    }
+    if (wv == 0) {
+        coef_group(lo + 16, 0);
+        creg0 = coef_fetch(cf, lo + 32, lmax, lane, 16);
+        creg1 = coef_fetch(cf, lo + 32, lmax, lane + 64, 16);
+    }
+    __syncthreads();
     int q = 0, l0 = lo;
     auto round = [&](auto mode) {
         v4 CN[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
@@ -511,9 +571,18 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
             // keep the operand loads within a few K steps of their use
             if (st % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
+        constexpr int kMode = decltype(mode)::value;
+        if (kMode != 2 && wv == 0) {
+            // publish the next round's coefficients (visible after this
+            // round's barrier), fetch the ones after them
+            cofb[q ^ 1][lane] = creg0;
+            cofb[q ^ 1][lane + 64] = creg1;
+            creg0 = coef_fetch(cf, l0 + 48, lmax, lane, 16);
+            creg1 = coef_fetch(cf, l0 + 48, lmax, lane + 64, 16);
+        }
         // the products have read the tile (LDS operations of a wave
         // complete in order): the next round's recursion overwrites it
-        if (l0 + 16 <= lmax) produce(l0 + 16, mode);
+        if (l0 + 16 <= lmax) produce(l0 + 16, q, mode);
         if (l0 > lo) reduce(l0 - 16, q ^ 1);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
