@@ -102,6 +102,7 @@ struct dm_plan {
     int mfma_nct = 1;                                 // column tiles (8 RHS each) of the batched kernels
     int mfma_mode = -1;                               // -1 auto, 0 off, 1 on (FP64 plans)
     int syn_threads = 128, syn_R = 1;
+    int syn_mchunk = 4, ana_mchunk = 4;               // batched kernels: consecutive m per XCD chunk
     int fft_threads = 512;
     size_t fft_lds_bytes = 0;
 

@@ -60,6 +60,34 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// Workgroup placement.  Workgroups go to the 8 XCDs (each with its own L2)
+// in turn by linear index, so a plain (pair block, m) grid spreads the
+// blocks of one m, which share their harmonic coefficients, recursion
+// coefficients and 128-byte lines of the ring data of neighbouring m, over
+// all XCDs.  The 1-D grid is decoded instead so that XCD c receives, in
+// order, chunks of kMChunk consecutive m with all their pair blocks:
+// m = R (8 j + c) + r, R = mchunk.  Indices past mmax return at once.
+// mchunk = 0 keeps the plain order (pair block fastest, then m).
+constexpr int kXcd = 8;
+
+struct BlockPos {
+    int x, m;
+};
+
+__device__ __forceinline__ BlockPos block_pos(int nx, int R) {
+    const int id = blockIdx.x;
+    if (R == 0) return BlockPos{id % nx, id / nx};
+    const int c = id % kXcd, k = id / kXcd;
+    const int j = k / (R * nx), r = (k / nx) % R, x = k % nx;
+    return BlockPos{x, R * (kXcd * j + c) + r};
+}
+
+inline unsigned grid_blocks(int nx, int mmax, int R) {
+    if (R == 0) return (unsigned)(nx * (mmax + 1));
+    const int chunks = (mmax + 1 + kXcd * R - 1) / (kXcd * R);
+    return (unsigned)(chunks * kXcd * R * nx);
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -68,6 +96,8 @@ __device__ __forceinline__ void wave_sync() {
 
 struct BatchArgs {
     int lmax, mmax, npairs, nrhs;
+    int nx;                         // ring-pair blocks per m
+    int mchunk;                     // consecutive m per XCD chunk (0: plain order)
     int64_t nalm;
     const double* __restrict__ pair_x;
     const double* __restrict__ coef;
@@ -226,10 +256,12 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     constexpr int PW = 8 * RT;                        // ring pairs per wave
     __shared__ SynTile<T, RT> tile[kSynWaves][2];
     __shared__ double cofw[kSynWaves][2][64];
-    const int m = blockIdx.y;
+    const BlockPos bp = block_pos(A.nx, A.mchunk);
+    const int m = bp.m;
+    if (m > A.mmax) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int pbase = (blockIdx.x * kSynWaves + wv) * PW;
-    const int rb = blockIdx.z * 8;
+    const int pbase = (bp.x * kSynWaves + wv) * PW;
+    const int rb = blockIdx.y * 8;
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefStride;
@@ -417,10 +449,12 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
     __shared__ T red[2][W][3 * kRedF];
     __shared__ double cofb[2][128];                     // recursion coefficients of 16 degrees
     __shared__ int s_lo[W], s_hi[W];
-    const int m = blockIdx.y;
+    const BlockPos bp = block_pos(A.nx, A.mchunk);
+    const int m = bp.m;
+    if (m > A.mmax) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int pbase = (blockIdx.x * W + wv) * kAnaPW;
-    const int rb = blockIdx.z * 8;
+    const int pbase = (bp.x * W + wv) * kAnaPW;
+    const int rb = blockIdx.y * 8;
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefStride;
@@ -464,7 +498,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
     if (m < 2) hi = max(hi, 2);
 
     const int nrhs = A.nrhs;
-    double* out = partial + ((int64_t)blockIdx.x * nrhs * 3) * A.nalm * 2;
+    double* out = partial + ((int64_t)bp.x * nrhs * 3) * A.nalm * 2;
     const int ncol = min(8, nrhs - rb);
     // degrees below the block's first active one: zero partial sums
     // (consecutive threads write consecutive (l, re/im))
@@ -611,6 +645,8 @@ BatchArgs batch_args(dm_plan* p, int nrhs) {
     a.lstart = p->d_lstart;
     a.seed = p->d_seed;
     a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
+    a.nx = 1;
+    a.mchunk = 0;
     return a;
 }
 
@@ -627,9 +663,11 @@ int batched_analysis_slots(dm_plan* p) {
 }
 
 hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
-    const BatchArgs A = batch_args(p, nrhs);
+    BatchArgs A = batch_args(p, nrhs);
     const int rt = p->precision == DM_MIXED ? 8 : 4;
-    dim3 grid((p->npairs + 8 * rt * kSynWaves - 1) / (8 * rt * kSynWaves), p->mmax + 1, (nrhs + 7) / 8);
+    A.nx = (p->npairs + 8 * rt * kSynWaves - 1) / (8 * rt * kSynWaves);
+    A.mchunk = p->syn_mchunk;
+    dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
     dim3 block(64 * kSynWaves);
     const double2* sp = reinterpret_cast<const double2*>(spin);
     if (p->precision == DM_MIXED) hipLaunchKernelGGL((bsyn_kernel<float, 8>), grid, block, 0, s, A, sp, phase);
@@ -639,8 +677,10 @@ hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, 
 
 hipError_t launch_bana(dm_plan* p, int nrhs, const double* phase, const double* pair_w, double* partial,
                        hipStream_t s) {
-    const BatchArgs A = batch_args(p, nrhs);
-    dim3 grid(batched_analysis_slots(p), p->mmax + 1, (nrhs + 7) / 8);
+    BatchArgs A = batch_args(p, nrhs);
+    A.nx = batched_analysis_slots(p);
+    A.mchunk = p->ana_mchunk;
+    dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
     const double2* ph = reinterpret_cast<const double2*>(phase);
     if (p->precision == DM_MIXED)
         hipLaunchKernelGGL((bana_kernel<float, kAnaWaves>), grid, dim3(64 * kAnaWaves), 0, s, A, ph, pair_w, partial);
