@@ -31,6 +31,11 @@ struct RingArgs {
     const double2* __restrict__ tw;
 };
 
+// LDS layout of a transform buffer: element i at i + i/8, so that the
+// stride-8 and stride-64 element groups of the first radix-8 passes fall in
+// distinct banks (one 16-byte pad per 128 bytes)
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -78,7 +83,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int M, int s, int logMmax
         const int base = ((q >> s) << (s + R)) + j;
         double2 x[G];
 #pragma unroll
-        for (int c = 0; c < G; ++c) x[c] = buf[base + c * h];
+        for (int c = 0; c < G; ++c) x[c] = buf[pidx(base + c * h)];
         double2 wb[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
@@ -105,7 +110,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, int M, int s, int logMmax
             }
         }
 #pragma unroll
-        for (int c = 0; c < G; ++c) buf[base + c * h] = x[c];
+        for (int c = 0; c < G; ++c) buf[pidx(base + c * h)] = x[c];
     }
     __syncthreads();
 }
@@ -135,7 +140,7 @@ __device__ void dft_core(double2* buf, const FftLenDev& L, const RingArgs& A) {
     } else {
         fft_dit(buf, L.M, L.logM, A.logMmax, A.tw, false);
         const double2* bh = A.bhat + L.bhat_off;
-        for (int q = threadIdx.x; q < L.M; q += blockDim.x) buf[q] = cmul(buf[q], bh[q]);
+        for (int q = threadIdx.x; q < L.M; q += blockDim.x) buf[pidx(q)] = cmul(buf[pidx(q)], bh[q]);
         __syncthreads();
         fft_dif(buf, L.M, L.logM, A.logMmax, A.tw, true);
     }
@@ -193,14 +198,14 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs A, const double* __r
                     v = make_double2(cn.x - cs.y, -(cn.y + cs.x));
                     if (L.bluestein) v = cmul(v, chirp[j]);
                 }
-                buf[k] = v;
+                buf[pidx(k)] = v;
             }
             __syncthreads();
             idft_core(buf, L, A);
             // now x_j (packed N + i S) = conj(buf[brev(j)] * chirp_j)
             for (int j = tid; j < n; j += nt) {
                 const int q = (int)brev(j, logM);
-                double2 y = buf[q];
+                double2 y = buf[pidx(q)];
                 if (L.bluestein) y = cmul(y, chirp[j]);
                 const double xn = y.x, xs = -y.y;
                 if (MODE == RING_SYNTH) {
@@ -220,11 +225,11 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs A, const double* __r
                     }
                     double2 a = make_double2(tn, ts);
                     if (L.bluestein) a = cmul(a, chirp[j]);
-                    buf[q] = a;
+                    buf[pidx(q)] = a;
                 }
             }
             if (MODE == RING_ITERATE && L.bluestein) {
-                for (int j = n + tid; j < M; j += nt) buf[brev(j, logM)] = make_double2(0.0, 0.0);
+                for (int j = n + tid; j < M; j += nt) buf[pidx((int)brev(j, logM))] = make_double2(0.0, 0.0);
             }
             __syncthreads();
         }
@@ -237,7 +242,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs A, const double* __r
                     a.y = P.has_s ? map_in[moff + P.off_s + j] : 0.0;
                     if (L.bluestein) a = cmul(a, chirp[j]);
                 }
-                buf[q] = a;
+                buf[pidx(q)] = a;
             }
             __syncthreads();
         }
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs A, const double* __r
                 const int k2 = (n - k) % n;
                 const int q1 = L.bluestein ? (int)brev(k, logM) : k;
                 const int q2 = L.bluestein ? (int)brev(k2, logM) : k2;
-                double2 z1 = buf[q1], z2 = buf[q2];
+                double2 z1 = buf[pidx(q1)], z2 = buf[pidx(q2)];
                 if (L.bluestein) { z1 = cmul(z1, chirp[k]); z2 = cmul(z2, chirp[k2]); }
                 // X_N = (Z_k + conj Z_{-k}) / 2,  X_S = (Z_k - conj Z_{-k}) / (2i)
                 const double2 xn = make_double2(0.5 * (z1.x + z2.x), 0.5 * (z1.y - z2.y));
