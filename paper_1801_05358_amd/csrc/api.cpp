@@ -173,6 +173,15 @@ void alm2map_dev(dm_plan* p, int nrhs, const double* alm, double* map, hipStream
     ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, p->d_phase, s);
 }
 
+// runs the transforms of a scope in another precision (the mixed plan's
+// FP64 epilogue: the returned map and the residual)
+struct PrecisionScope {
+    dm_plan* p;
+    dm_precision saved;
+    PrecisionScope(dm_plan* p_, dm_precision pr) : p(p_), saved(p_->precision) { p->precision = pr; }
+    ~PrecisionScope() { p->precision = saved; }
+};
+
 void check_rhs(dm_plan* p, int nrhs) {
     REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, DM_EINVAL,
             "nrhs must be in [1, max_rhs=" + std::to_string(p->max_rhs) + "]");
@@ -255,6 +264,13 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
             }
         }
+    }
+    // epilogue in FP64 (section a8): a mixed plan recomputes s_x = Y u with
+    // the FP64 transforms before it is returned or enters the residual
+    std::unique_ptr<PrecisionScope> fp64;
+    if (p->precision == DM_MIXED && (map || stats)) {
+        fp64.reset(new PrecisionScope(p, DM_FP64));
+        alm2map_dev(p, nrhs, alm, p->d_ux, s);
     }
     if (map) HIPCHK(hipMemcpyAsync(map, p->d_ux, (size_t)nrhs * 3 * p->npix * sizeof(double),
                                    hipMemcpyDeviceToDevice, s));
@@ -494,7 +510,15 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         // work buffers
         const size_t B = (size_t)max_rhs;
         dalloc(p, p->d_phase, B * 3 * p->npairs * (p->mmax + 1) * 4);
-        const size_t slots = (size_t)std::max(p->ana_chunks, batched_analysis_slots(p));
+        // partial-sum slots for every kernel the plan may run (a mixed plan
+        // also runs the FP64 batched kernels for its FP64 epilogue)
+        size_t slots = (size_t)std::max(p->ana_chunks, batched_analysis_slots(p));
+        {
+            const dm_precision pr = p->precision;
+            p->precision = DM_FP64;
+            slots = std::max(slots, (size_t)batched_analysis_slots(p));
+            p->precision = pr;
+        }
         dalloc(p, p->d_partial, slots * B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_prev, B * 3 * p->nalm * 2);

@@ -202,59 +202,66 @@ __device__ __forceinline__ void rec_next(const double* __restrict__ cf, int l, R
 }
 
 // ---------------------------------------------------------------------------
-// synthesis: 4 waves x (8 RT) ring pairs per block, rounds of 4 degrees;
-// one column tile of 8 RHS per block.  The producer writes two copies of
-// the round's functions: north rows (lam, p, q) and south rows
-// eps (lam, q, p), so that every A operand is a plain LDS read.
+// synthesis: 4 waves x PW ring pairs per block (PW = 64 FP32, 32 FP64),
+// rounds of 4 degrees (one K step), one column tile of 8 RHS per block.
+// The rows of one matrix instruction are 16 ring pairs of one side: the
+// north rows take (lam, +2lam, -2lam) times D_f, the mirror rows
+// (lam, -2lam, +2lam) times eps_l D_f, with the sign on the B operand (per
+// lane, fixed for the kernel since rounds advance by 4 degrees).
 // ---------------------------------------------------------------------------
 constexpr int kSynWaves = 4;
 
-// [side][A_T, A_+2, A_-2][degree in round][pair], padded so that the 64
-// operand reads of one matrix instruction (2 sides x 4 degrees x 8 pairs)
-// fall in distinct LDS banks: degree rows 8 words apart modulo 32, sides 16
-// (FP32); FP64 values take two banks and are read 16 lanes at a time,
-// which needs the sides 8 doubles apart modulo 16
-template <typename T, int RT>
+// [f = lam, +2, -2][degree in round][pair]; FP32 operand reads of one
+// instruction (16 pairs x 4 degrees, 32 lanes at a time) are conflict-free
+// with rows 16 words apart modulo 32; FP64 reads go 16 lanes (one degree)
+// at a time and need no padding
+template <typename T, int PW>
 struct SynTile {
-    static constexpr int K = sizeof(T) == 4 ? 8 * RT + 8 : 8 * RT;
+    static constexpr int K = sizeof(T) == 4 ? PW + 16 : PW;
     static constexpr int F = 4 * K;
-    static constexpr int S = sizeof(T) == 4 ? 3 * F + 16 : 3 * F + 8;
-    T v[2 * S];
-    __device__ T& at(int side, int f, int j, int pair) { return v[side * S + f * F + j * K + pair]; }
-    __device__ const T& at(int side, int f, int j, int pair) const { return v[side * S + f * F + j * K + pair]; }
+    T v[3 * F];
+    __device__ T& at(int f, int j, int pair) { return v[f * F + j * K + pair]; }
+    __device__ const T& at(int f, int j, int pair) const { return v[f * F + j * K + pair]; }
 };
 
-template <typename T, int RT>
-__device__ __forceinline__ void bsyn_mfma(const SynTile<T, RT>& tl, int k, int pl, int side, const T (&b)[3],
-                                          typename Mfma<T>::v4 (&acc)[RT][3]) {
+// per-wave LDS: two tiles, reused by the epilogue as staging for one row
+// tile of outputs, [f][16 pairs][8 RHS][side][re/im]
+template <typename T, int PW>
+constexpr int syn_wave_bytes() {
+    return 2 * (int)sizeof(SynTile<T, PW>) > 1536 * (int)sizeof(T) ? 2 * (int)sizeof(SynTile<T, PW>)
+                                                                    : 1536 * (int)sizeof(T);
+}
+
+template <typename T, int PW>
+__device__ __forceinline__ void syn_store(SynTile<T, PW>& tl, int j, int pair, double lam, double pp, double qq) {
+    tl.at(0, j, pair) = (T)lam;
+    tl.at(1, j, pair) = (T)pp;
+    tl.at(2, j, pair) = (T)qq;
+}
+
+template <typename T, int PW>
+__device__ __forceinline__ void bsyn_mfma(const SynTile<T, PW>& tl, int k, int row, const T (&b)[3], const T (&bs)[3],
+                                          typename Mfma<T>::v4 (&acc)[PW / 16][2][3]) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-        const int pi = t * 8 + pl;
-        const T aT = tl.at(side, 0, k, pi), aP = tl.at(side, 1, k, pi), aM = tl.at(side, 2, k, pi);
-        acc[t][0] = Mfma<T>::run(aT, b[0], acc[t][0]);
-        acc[t][1] = Mfma<T>::run(aP, b[1], acc[t][1]);
-        acc[t][2] = Mfma<T>::run(aM, b[2], acc[t][2]);
+    for (int t = 0; t < PW / 16; ++t) {
+        const int pi = t * 16 + row;
+        const T l = tl.at(0, k, pi), pp = tl.at(1, k, pi), qq = tl.at(2, k, pi);
+        acc[t][0][0] = Mfma<T>::run(l, b[0], acc[t][0][0]);
+        acc[t][0][1] = Mfma<T>::run(pp, b[1], acc[t][0][1]);
+        acc[t][0][2] = Mfma<T>::run(qq, b[2], acc[t][0][2]);
+        acc[t][1][0] = Mfma<T>::run(l, bs[0], acc[t][1][0]);
+        acc[t][1][1] = Mfma<T>::run(qq, bs[1], acc[t][1][1]);
+        acc[t][1][2] = Mfma<T>::run(pp, bs[2], acc[t][1][2]);
     }
 }
 
-template <typename T, int RT>
-__device__ __forceinline__ void syn_store(SynTile<T, RT>& tl, int j, int lane, bool odd, double lam, double pp,
-                                          double qq) {
-    const T a = (T)lam, b = (T)pp, c = (T)qq;
-    tl.at(0, 0, j, lane) = a;
-    tl.at(0, 1, j, lane) = b;
-    tl.at(0, 2, j, lane) = c;
-    tl.at(1, 0, j, lane) = odd ? -a : a;
-    tl.at(1, 1, j, lane) = odd ? -c : c;
-    tl.at(1, 2, j, lane) = odd ? -b : b;
-}
-
-template <typename T, int RT>
+template <typename T, int PW>
 __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const double2* __restrict__ spin,
                                                               double* __restrict__ phase) {
     typedef typename Mfma<T>::v4 v4;
-    constexpr int PW = 8 * RT;                        // ring pairs per wave
-    __shared__ SynTile<T, RT> tile[kSynWaves][2];
+    constexpr int NT = PW / 16;                       // row tiles per side
+    constexpr int WB = syn_wave_bytes<T, PW>();
+    __shared__ __align__(16) unsigned char lds[kSynWaves][WB];
     __shared__ double cofw[kSynWaves][2][64];
     const BlockPos bp = block_pos(A.nx, A.mchunk);
     const int m = bp.m;
@@ -265,6 +272,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefStride;
+    SynTile<T, PW>* tile = reinterpret_cast<SynTile<T, PW>*>(&lds[wv][0]);
     // the ring pair this lane recurses; with PW < 64 the upper lanes repeat
     // the lower ones and store the same values to the same addresses
     const int me = lane % PW;
@@ -275,17 +283,20 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     int hi = __builtin_amdgcn_readfirstlane(wave_max(s.ls <= lmax ? s.ls : 0));
     if (m < 2) hi = max(hi, 2);
 
-    v4 acc[RT][3];
+    v4 acc[NT][2][3];
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int f = 0; f < 3; ++f) acc[t][f] = v4{0, 0, 0, 0};
+        for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) acc[t][sd][f] = v4{0, 0, 0, 0};
 
     const int row = lane & 15, k = lane >> 4;
-    const int side = row & 1, pl = row >> 1;
     const int col = lane & 15, ri = col & 1;
     const int rhs = rb + (col >> 1);
     const bool rhs_ok = rhs < A.nrhs;
+    // eps of this lane's degree l0 + k (rounds start at lo + 4n)
+    const T eps = ((lo + k + m) & 1) ? (T)-1 : (T)1;
     // padding columns read RHS 0 and are never stored
     const double* __restrict__ sbase = reinterpret_cast<const double*>(spin) +
                                        (((int64_t)(rhs_ok ? rhs : 0) * 3) * A.nalm + base) * 2 + ri;
@@ -299,7 +310,14 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         for (int j = 0; j < 4; ++j) {
             double lam, pp, qq;
             rec_step(A, cf, m, l0 + j, lo, hi, s, lam, pp, qq);
-            syn_store<T, RT>(tile[wv][q], j, me, (l0 + j + m) & 1, lam, pp, qq);
+            syn_store<T, PW>(tile[q], j, me, lam, pp, qq);
+        }
+    };
+    auto operands = [&](const double (&braw)[3], T (&b)[3], T (&bs)[3]) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            b[f] = (T)braw[f];
+            bs[f] = eps * b[f];
         }
     };
 
@@ -313,11 +331,10 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         for (; l0 <= lmax; l0 += 4, q ^= 1) {
             const int ln = l0 + 4;
             if (ln > hi && ln + 3 <= lmax) break;
-            T b[3];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+            T b[3], bs[3];
+            operands(braw, b, bs);
             load_b(ln + k, braw);
-            bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+            bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
             if (ln <= lmax) produce_any(ln, q ^ 1);
             wave_sync();
         }
@@ -330,19 +347,18 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
             wave_sync();
             int cs = 0;
             for (; l0 + 7 <= lmax; l0 += 4, q ^= 1, cs ^= 1) {
-                T b[3];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+                T b[3], bs[3];
+                operands(braw, b, bs);
                 // the in-flight group (degrees l0 + 8 ..) to the other slot,
                 // then the group after it, then the next B operands
                 cofw[wv][cs ^ 1][lane] = creg;
                 creg = coef_fetch(cf, l0 + 12, lmax, lane, 4);
                 load_b(l0 + 4 + k, braw);
-                bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+                bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     rec_advance(coef_lds(&cofw[wv][cs][j * kCoefN]), s);
-                    syn_store<T, RT>(tile[wv][q ^ 1], j, me, (l0 + 4 + j + m) & 1, s.l1, s.w1, s.q1);
+                    syn_store<T, PW>(tile[q ^ 1], j, me, s.l1, s.w1, s.q1);
                 }
                 wave_sync();
             }
@@ -350,61 +366,64 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         // tail
         for (; l0 <= lmax; l0 += 4, q ^= 1) {
             const int ln = l0 + 4;
-            T b[3];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) b[f] = (T)braw[f];
+            T b[3], bs[3];
+            operands(braw, b, bs);
             load_b(ln + k, braw);
-            bsyn_mfma<T, RT>(tile[wv][q], k, pl, side, b, acc);
+            bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
             if (ln <= lmax) produce_any(ln, q ^ 1);
             wave_sync();
         }
     }
 
-    // epilogue, through the wave's (now free) tile: per 8 ring pairs the
-    // raw products go to LDS as [f][pair][rhs][side][re/im]; then each lane
-    // takes one (pair, rhs), forms T, Q = (P + M)/2, U = (P - M)/(2i) and
-    // writes 32 contiguous bytes (both sides, re/im) per field
-    double* stg = reinterpret_cast<double*>(&tile[wv][0]);
-    static_assert(sizeof(SynTile<T, RT>) * 2 >= 3 * 8 * 8 * 4 * sizeof(double), "staging does not fit");
+    // epilogue, through the wave's (now free) LDS: per row tile (16 ring
+    // pairs) the raw products go to LDS as [f][pair][rhs][side][re/im]; then
+    // each lane takes two (pair, rhs), forms T, Q = (P + M)/2,
+    // U = (P - M)/(2i) and writes 32 contiguous bytes (both sides, re/im)
+    // per field
+    T* stg = reinterpret_cast<T*>(&lds[wv][0]);
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 4;     // doubles per field
-    const int pl_r = lane >> 3, rc_r = lane & 7;
-    const int rhs_w = rb + rc_r;
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
+    for (int t = 0; t < NT; ++t) {
         wave_sync();
 #pragma unroll
-        for (int f = 0; f < 3; ++f)
+        for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = Mfma<T>::row(lane, v);
-                stg[((f * 8 + (r >> 1)) * 8 + (col >> 1)) * 4 + (r & 1) * 2 + ri] = (double)acc[t][f][v];
-            }
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = Mfma<T>::row(lane, v);
+                    stg[(((f * 16 + r) * 8 + (col >> 1)) * 2 + sd) * 2 + ri] = acc[t][sd][f][v];
+                }
         wave_sync();
-        const int pair = pbase + t * 8 + pl_r;
-        if (pair < A.npairs && rhs_w < A.nrhs) {
-            const double* g = stg + (pl_r * 8 + rc_r) * 4;
-            const double2 tn = {g[0], g[1]}, ts = {g[2], g[3]};
-            const double* gp = g + 8 * 8 * 4;
-            const double* gm = g + 2 * 8 * 8 * 4;
-            double qv[4], uv[4];
 #pragma unroll
-            for (int sd = 0; sd < 2; ++sd) {
-                const double pr = gp[2 * sd], pi = gp[2 * sd + 1], mr = gm[2 * sd], mi = gm[2 * sd + 1];
-                qv[2 * sd] = 0.5 * (pr + mr);
-                qv[2 * sd + 1] = 0.5 * (pi + mi);
-                uv[2 * sd] = 0.5 * (pi - mi);
-                uv[2 * sd + 1] = -0.5 * (pr - mr);
+        for (int h = 0; h < 2; ++h) {
+            const int u = lane + 64 * h;
+            const int r = u >> 3, rc = u & 7;
+            const int pair = pbase + t * 16 + r, rw = rb + rc;
+            if (pair < A.npairs && rw < A.nrhs) {
+                const T* g = stg + (r * 8 + rc) * 4;
+                const T* gp = g + 16 * 8 * 4;
+                const T* gm = g + 2 * 16 * 8 * 4;
+                double qv[4], uv[4];
+#pragma unroll
+                for (int sd = 0; sd < 2; ++sd) {
+                    const double pr = gp[2 * sd], pi = gp[2 * sd + 1], mr = gm[2 * sd], mi = gm[2 * sd + 1];
+                    qv[2 * sd] = 0.5 * (pr + mr);
+                    qv[2 * sd + 1] = 0.5 * (pi + mi);
+                    uv[2 * sd] = 0.5 * (pi - mi);
+                    uv[2 * sd + 1] = -0.5 * (pr - mr);
+                }
+                double2* o = reinterpret_cast<double2*>(
+                    phase + ((((int64_t)rw * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 4);
+                o[0] = double2{(double)g[0], (double)g[1]};
+                o[1] = double2{(double)g[2], (double)g[3]};
+                double2* oq = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + fstride);
+                oq[0] = double2{qv[0], qv[1]};
+                oq[1] = double2{qv[2], qv[3]};
+                double2* ou = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + 2 * fstride);
+                ou[0] = double2{uv[0], uv[1]};
+                ou[1] = double2{uv[2], uv[3]};
             }
-            double2* o = reinterpret_cast<double2*>(
-                phase + ((((int64_t)rhs_w * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 4);
-            o[0] = tn;
-            o[1] = ts;
-            double2* oq = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + fstride);
-            oq[0] = double2{qv[0], qv[1]};
-            oq[1] = double2{qv[2], qv[3]};
-            double2* ou = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + 2 * fstride);
-            ou[0] = double2{uv[0], uv[1]};
-            ou[1] = double2{uv[2], uv[3]};
         }
     }
 }
@@ -664,14 +683,14 @@ int batched_analysis_slots(dm_plan* p) {
 
 hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
     BatchArgs A = batch_args(p, nrhs);
-    const int rt = p->precision == DM_MIXED ? 8 : 4;
-    A.nx = (p->npairs + 8 * rt * kSynWaves - 1) / (8 * rt * kSynWaves);
+    const int pw = p->precision == DM_MIXED ? 64 : 32;
+    A.nx = (p->npairs + pw * kSynWaves - 1) / (pw * kSynWaves);
     A.mchunk = p->syn_mchunk;
     dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
     dim3 block(64 * kSynWaves);
     const double2* sp = reinterpret_cast<const double2*>(spin);
-    if (p->precision == DM_MIXED) hipLaunchKernelGGL((bsyn_kernel<float, 8>), grid, block, 0, s, A, sp, phase);
-    else hipLaunchKernelGGL((bsyn_kernel<double, 4>), grid, block, 0, s, A, sp, phase);
+    if (p->precision == DM_MIXED) hipLaunchKernelGGL((bsyn_kernel<float, 64>), grid, block, 0, s, A, sp, phase);
+    else hipLaunchKernelGGL((bsyn_kernel<double, 32>), grid, block, 0, s, A, sp, phase);
     return hipGetLastError();
 }
 

@@ -130,3 +130,26 @@ def test_mixed_solve_config1_full_schedule(dmwf):
         errs = [rel_alm(out["alm"][k], ref, p["lmax"], f) for f in range(3)]
         print("mixed cfg1 per-field rel err", errs, flush=True)
         assert max(errs) < 1e-5, errs
+
+
+def test_mixed_epilogue_is_fp64(dmwf):
+    """The mixed plan's returned map s_x = Y u and its residual and chi^2 are
+    computed with the FP64 transforms (the epilogue of the iteration): they
+    match the oracle's FP64 evaluation at the mixed solution u to FP64
+    rounding, not to the 1e-5 of the mixed contraction."""
+    nrhs = 2
+    p, grid, sht, D = cfg1_inputs(nrhs)
+    plan = dmwf.Plan(lmax=p["lmax"], nside=p["nside"], max_rhs=nrhs, precision=dmwf.MIXED)
+    plan.set_spectra(p["cl"])
+    plan.set_noise(p["ncov"], p["obs"])
+    plan.set_schedule(1e3, 3, 4)
+    out = plan.wiener_filter(D, want_map=True, want_stats=True)
+    for k in range(nrhs):
+        u = out["alm"][k]
+        ref_map = sht.synthesis(u)
+        assert rel_map(out["map"][k], ref_map) < 1e-12, k
+        res = dm.residual(sht, u, D[k], p["ncov"], p["obs"], p["cl"])
+        chi = dm.chi2(sht, u, D[k], p["ncov"], p["obs"], p["cl"])
+        st = out["stats"][k]
+        assert abs(st["residual"] - res) <= 1e-10 * res, (st["residual"], res)
+        assert abs(st["chi2"] - chi) <= 1e-10 * chi, (st["chi2"], chi)
