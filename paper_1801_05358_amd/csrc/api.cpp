@@ -323,7 +323,8 @@ void free_plan(dm_plan* p) {
         (void)hipEventDestroy(p->ev.stop[i]);
     }
     dfree(p->d_pair_x); dfree(p->d_pair_w); dfree(p->d_pair_one); dfree(p->d_pairs); dfree(p->d_fftlen);
-    dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
+    dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
+    dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
@@ -462,6 +463,18 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         if (!p->fft.chirp.empty()) upload(p, p->d_chirp, p->fft.chirp.data(), p->fft.chirp.size());
         if (!p->fft.bhat.empty()) upload(p, p->d_bhat, p->fft.bhat.data(), p->fft.bhat.size());
         upload(p, p->d_tw, p->fft.tw.data(), p->fft.tw.size());
+        if (precision == DM_MIXED) {
+            // the ring transforms of a mixed plan run in FP32
+            auto to32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+            const std::vector<float> c32 = to32(p->fft.chirp), b32 = to32(p->fft.bhat), t32 = to32(p->fft.tw);
+            dalloc(p, p->d_chirp32, c32.size());
+            dalloc(p, p->d_bhat32, b32.size());
+            dalloc(p, p->d_tw32, t32.size());
+            if (!c32.empty()) upload(p, p->d_chirp32, c32.data(), c32.size());
+            if (!b32.empty()) upload(p, p->d_bhat32, b32.data(), b32.size());
+            upload(p, p->d_tw32, t32.data(), t32.size());
+            HIPCHK(hipStreamSynchronize(p->stream));           // the host copies go out of scope
+        }
         HIPCHK(ring_set_lds_limit(p->fft_lds_bytes));
         std::vector<int64_t> roff(p->rings.offset.begin(), p->rings.offset.end());
         dalloc(p, p->d_ring_w, p->nrings);

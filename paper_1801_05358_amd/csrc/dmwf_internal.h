@@ -91,6 +91,9 @@ struct dm_plan {
     double* d_chirp = nullptr;
     double* d_bhat = nullptr;
     double* d_tw = nullptr;
+    float* d_chirp32 = nullptr;        // FP32 copies of the three tables (mixed plans)
+    float* d_bhat32 = nullptr;
+    float* d_tw32 = nullptr;
     double* d_coef = nullptr;          // [nalm][kCoefStride]
     int* d_lstart = nullptr;           // [mmax+1][npairs]
     double* d_seed = nullptr;          // [kSeedFields][mmax+1][npairs]
