@@ -21,9 +21,9 @@ namespace dmwf {
 
 namespace {
 
-// complex values of the transform's real type R (FP64, or FP32 for the
-// mixed plans: the FFTs in LDS and the fold/unfold run in R, the ring data
-// in HBM and the pixel update t = K x + b stay FP64)
+// complex values of the transform's real type R (FP64, or FP32 for mixed
+// plans that ask for it: the FFTs in LDS and the fold/unfold run in R, the
+// ring data in HBM and the pixel update t = K x + b stay FP64)
 template <typename R>
 struct V2;
 template <>
@@ -362,7 +362,8 @@ hipError_t set_lds_t(size_t bytes) {
 
 }  // namespace
 
-// FP32 transforms for mixed plans (their tables exist), FP64 otherwise
+// FP32 transforms for mixed plans that carry the FP32 tables (opt-in at
+// plan creation), FP64 otherwise
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
                        const double* b, double* phase, hipStream_t s) {
     double2* ph = reinterpret_cast<double2*>(phase);
