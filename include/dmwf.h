@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 1
+#define DMWF_ABI_VERSION 2
 
 typedef enum {
     DM_OK = 0,
@@ -81,14 +81,30 @@ typedef struct {
     int nphi;      /* pixels per Gauss-Legendre ring (kind 1)             */
 } dm_grid;
 
-/* Cooling schedule (Algorithm 1, Sec. 3.2): xi_k = lambda_k * tau with
- * lambda_k = lambda_start^(1 - k/(nsteps-1)), k = 0..nsteps-1 (the last
- * step has lambda = 1, i.e. mu = 0), and iters_per_step iterations per
- * step.  nsteps = 1 runs only lambda = 1.                                  */
+/* Cooling schedule (Algorithm 1, Sec. 3.2), xi = lambda * tau, in one of
+ * two modes.
+ *
+ * Fixed mode (iters_per_step >= 1): lambda_k = lambda_start^(1 - k/(nsteps-1)),
+ * k = 0..nsteps-1 (the last step has lambda = 1, i.e. mu = 0), with
+ * iters_per_step iterations per step; nsteps = 1 runs only lambda = 1.
+ *
+ * Epsilon mode (iters_per_step <= 0): Algorithm 1's own loop.  lambda_j =
+ * lambda_start * beta^j while above 1, then a last step at lambda = 1; at
+ * step j the iteration repeats until the Cauchy ratio
+ * ||u_i - u_{i-1}|| / ||u_i|| (harmonic L2 over T, E, B with m > 0 counted
+ * twice; u_0 = 0; the largest over the right-hand sides of a batch) falls
+ * below eps_j = max(eps_end, eps_start * eps_eta^-j), and below eps_end at
+ * the last step (the threshold cooling of Sec. 3.2); the solve stops early
+ * after max_iters iterations in total.  nsteps is ignored.               */
 typedef struct {
     double lambda_start;   /* >= 1                                          */
-    int nsteps;            /* >= 1                                          */
-    int iters_per_step;    /* >= 1                                          */
+    int nsteps;            /* fixed mode: >= 1                              */
+    int iters_per_step;    /* fixed mode: >= 1; <= 0 selects epsilon mode   */
+    double beta;           /* epsilon mode: cooling factor, 0 < beta < 1    */
+    double eps_start;      /* epsilon mode: first threshold, >= eps_end     */
+    double eps_end;        /* epsilon mode: final threshold, > 0            */
+    double eps_eta;        /* epsilon mode: relaxation per step, >= 1       */
+    int max_iters;         /* epsilon mode: cap on the total, >= 1          */
 } dm_schedule;
 
 /* Per right-hand side diagnostics.  residual = ||A x - y|| / ||y|| with
@@ -137,8 +153,16 @@ dm_status dm_set_spectra(dm_plan* plan, const double* cl);
  * pixel weight), the messenger covariance of eq 4.                       */
 dm_status dm_set_noise(dm_plan* plan, const double* ncov, dm_ncov layout, const uint8_t* obs);
 
-/* Cooling schedule; the default is {1e3, 20, 10}.                          */
+/* Cooling schedule; the default is the fixed mode {1e3, 20, 10}.          */
 dm_status dm_set_schedule(dm_plan* plan, const dm_schedule* schedule);
+
+/* Per-iteration record of the last solve in epsilon mode (Fig. 4's Cauchy
+ * trace): cauchy[i] = the Cauchy ratio after iteration i (largest over the
+ * right-hand sides), step[i] = its cooling step.  Copies min(cap, n)
+ * entries into the caller's host arrays (either may be NULL) and sets *n to
+ * the iteration count; *n = 0 after a fixed-mode solve.  Errors: DM_EINVAL
+ * for a null plan or n.                                                    */
+dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int cap, int* n);
 
 /* Wiener filter of nrhs data maps d [nrhs][3][npix] (Algorithm 1).  Writes
  * the final iterate u (the Wiener-filtered T, E, B alm) to alm

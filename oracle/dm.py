@@ -21,6 +21,9 @@ Follows the paper step by step (Kodi Ramanah, Lavaux & Wandelt 2018):
   until mu = 0.  The cooling uses lambda_k = xi_k / tau, geometric from
   lambda_0 down to exactly 1 over the given number of steps, with a fixed
   number of iterations per step;
+* the paper's own stopping rule (Algorithm 1, Sec. 3.2): per cooling step
+  iterate until the Cauchy ratio drops below a threshold that is itself
+  cooled by a factor eta per step, xi <- beta xi until mu = 0;
 * diagnostics: the Cauchy ratio of Algorithm 1's stopping rule, the residual
   ||A x - y|| / ||y|| with A = 1 + S^1/2 N^-1 S^1/2 (Appendix C; here
   x = S^-1/2 u, y = S^1/2 Y^T N^-1 d) and the chi^2 of eq 3;
@@ -124,6 +127,62 @@ def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False):
             u_prev = u
     return dict(u=u, ux=ux, tau=tau, cauchy=cauchy[-1] if cauchy else float("nan"),
                 trace=cauchy if trace else None, setup=st)
+
+
+def eps_schedule(lambda0, beta):
+    """The cooling of Algorithm 1 driven to its end: xi <- beta xi, i.e.
+    lambda_j = lambda0 beta^j while it is above 1, then a last step at
+    lambda = 1 (mu = 0)."""
+    lam = []
+    v = float(lambda0)
+    while v > 1.0:
+        lam.append(v)
+        v *= beta
+    lam.append(1.0)
+    return np.array(lam)
+
+
+def eps_thresholds(nsteps, eps_start, eps_end, eta):
+    """The cooled Cauchy threshold of Sec. 3.2: relaxed by eta per cooling
+    step, eps_j = max(eps_end, eps_start eta^-j), and eps_end at the last
+    step (lambda = 1)."""
+    eps = np.maximum(eps_end, eps_start * float(eta) ** -np.arange(nsteps, dtype=float))
+    eps[-1] = eps_end
+    return eps
+
+
+def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters):
+    """Algorithm 1 with its stopping rule: at each cooling step repeat the
+    iteration until ||u_i - u_{i-1}|| / ||u_i|| < eps_j (u_0 = 0, so every
+    step runs at least one iteration), then cool; stop early once max_iters
+    iterations have run in total.  Returns dict(u, ux, tau, iterations,
+    trace = per-iteration Cauchy ratios, steps = cooling step of each
+    iteration)."""
+    lmax = sht.lmax
+    st = setup(sht.grid, ncov, obs, d)
+    tau, K, b = st["tau"], st["K"], st["b"]
+    t = st["d0"].copy()
+    u_prev = np.zeros((3, lm_arrays(lmax)[0].size), dtype=complex)
+    lams = eps_schedule(lambda0, beta)
+    eps = eps_thresholds(len(lams), eps_start, eps_end, eta)
+    trace, steps = [], []
+    u = ux = None
+    for j, lam in enumerate(lams):
+        F = messenger_filter(cl, (lam - 1.0) * tau, tau)
+        while len(trace) < max_iters:
+            t_hat = sht.analysis(t)
+            u = apply_blocks(F, t_hat, lmax)
+            ux = sht.synthesis(u)
+            t = K * ux + b
+            c = cauchy_ratio(u, u_prev, lmax)
+            trace.append(c)
+            steps.append(j)
+            u_prev = u
+            if c < eps[j]:
+                break
+        if len(trace) >= max_iters:
+            break
+    return dict(u=u, ux=ux, tau=tau, iterations=len(trace), trace=trace, steps=steps, lambdas=lams, eps=eps)
 
 
 # ----------------------------------------------------------------------------

@@ -130,7 +130,7 @@ bool use_mfma(dm_plan* p, int nrhs) {
 }
 
 void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, const double* filter, double* alm,
-                  double* spin, hipStream_t s) {
+                  double* spin, hipStream_t s, double* cpart = nullptr) {
     const double* w = weighted ? p->d_pair_w : p->d_pair_one;
     int nslots = p->ana_chunks;
     {
@@ -145,7 +145,7 @@ void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, cons
         t.done();
     }
     Timed t(p, KC_COMBINE, s);
-    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, filter, alm, spin, s));
+    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, filter, alm, spin, cpart, s));
     t.done();
 }
 
@@ -210,7 +210,16 @@ void prepare_filters(dm_plan* p, const std::vector<double>& lambdas) {
     HIPCHK(hipMemcpyAsync(p->d_filters, p->h_pinned, need * sizeof(double), hipMemcpyHostToDevice, p->stream));
 }
 
+bool eps_mode(const dm_schedule& sc) { return sc.iters_per_step <= 0; }
+
 std::vector<double> schedule_lambdas(const dm_schedule& sc) {
+    if (eps_mode(sc)) {
+        // lambda_j = lambda_start beta^j while above 1, then 1
+        std::vector<double> lam;
+        for (double v = sc.lambda_start; v > 1.0; v *= sc.beta) lam.push_back(v);
+        lam.push_back(1.0);
+        return lam;
+    }
     std::vector<double> lam(sc.nsteps, 1.0);
     if (sc.nsteps > 1)
         for (int k = 0; k < sc.nsteps - 1; ++k)
@@ -244,24 +253,78 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     // setup: d0 = mask(d), b = T N^-1 d0, t_0 = d0
     HIPCHK(launch_data_setup(p, nrhs, d, p->d_d0, p->d_b, s));
     ring(p, RING_ANALYSIS, nrhs, p->d_d0, nullptr, nullptr, p->d_phase, s);
-    const int nsteps = (int)lam.size(), niter = p->sched.iters_per_step;
-    const int total = nsteps * niter;
-    int it = 0;
-    for (int k = 0; k < nsteps; ++k) {
-        const double* F = p->d_filters + per * k;
-        for (int i = 0; i < niter; ++i, ++it) {
-            const bool last = (it == total - 1);
-            if (last && stats) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_len * sizeof(double),
-                                                     hipMemcpyDeviceToDevice, s));
-            // t_hat = A t ; u = F t_hat        (eq 8)
-            leg_analysis(p, nrhs, p->d_phase, true, F, alm, p->d_alm_spin, s);
-            // u_x = Y u                          (synthesis)
-            leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
-            if (!last) {
-                // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
+    const int nsteps = (int)lam.size();
+    const bool eps = eps_mode(p->sched);
+    p->trace_cauchy.clear();
+    p->trace_step.clear();
+    int total = 0;
+    std::vector<double> last_c(nrhs, 0.0);
+    if (!eps) {
+        const int niter = p->sched.iters_per_step;
+        total = nsteps * niter;
+        int it = 0;
+        for (int k = 0; k < nsteps; ++k) {
+            const double* F = p->d_filters + per * k;
+            for (int i = 0; i < niter; ++i, ++it) {
+                const bool last = (it == total - 1);
+                if (last && stats) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_len * sizeof(double),
+                                                         hipMemcpyDeviceToDevice, s));
+                // t_hat = A t ; u = F t_hat        (eq 8)
+                leg_analysis(p, nrhs, p->d_phase, true, F, alm, p->d_alm_spin, s);
+                // u_x = Y u                          (synthesis)
+                leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
+                if (!last) {
+                    // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
+                    ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, p->d_phase, s);
+                } else {
+                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
+                }
+            }
+        }
+    } else {
+        // Algorithm 1's loop: per cooling step, repeat until the Cauchy ratio
+        // (largest over the RHS) is below that step's threshold.  The ratio
+        // of iteration i comes from the combine kernel; the host reads it
+        // while the GPU runs the iteration's synthesis, then picks the ring
+        // step: the pixel update, or (at the end) the final map.
+        const dm_schedule& sc = p->sched;
+        struct Ev {
+            hipEvent_t e = nullptr;
+            ~Ev() { if (e) (void)hipEventDestroy(e); }
+        } ev;
+        HIPCHK(hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
+        HIPCHK(hipMemsetAsync(alm, 0, alm_len * sizeof(double), s));          // u_0 = 0
+        bool done = false;
+        for (int k = 0; k < nsteps && !done; ++k) {
+            const double* F = p->d_filters + per * k;
+            const double thr = (k == nsteps - 1) ? sc.eps_end
+                                                 : std::max(sc.eps_end, sc.eps_start * std::pow(sc.eps_eta, -(double)k));
+            for (;;) {
+                leg_analysis(p, nrhs, p->d_phase, true, F, alm, p->d_alm_spin, s, p->d_cpart);
+                HIPCHK(launch_cauchy_reduce(p, nrhs, p->d_cpart, p->d_cout, s));
+                HIPCHK(hipMemcpyAsync(p->h_cout, p->d_cout, (size_t)nrhs * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                      s));
+                HIPCHK(hipEventRecord(ev.e, s));
+                leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
+                HIPCHK(hipEventSynchronize(ev.e));
+                double c = 0.0;
+                for (int r = 0; r < nrhs; ++r) {
+                    const double num = p->h_cout[2 * r], den = p->h_cout[2 * r + 1];
+                    last_c[r] = den > 0.0 ? std::sqrt(num / den) : 0.0;
+                    c = std::max(c, last_c[r]);
+                }
+                REQUIRE(std::isfinite(c), DM_ENONFINITE, "the iterate became non-finite");
+                p->trace_cauchy.push_back(c);
+                p->trace_step.push_back(k);
+                ++total;
+                const bool conv = c < thr;
+                if ((conv && k == nsteps - 1) || total >= sc.max_iters) {
+                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
+                    done = true;
+                    break;
+                }
                 ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, p->d_phase, s);
-            } else {
-                ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
+                if (conv) break;
             }
         }
     }
@@ -287,7 +350,8 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         map2alm_dev(p, nrhs, p->d_b, p->d_alm_y, false, s);
         const int nb = alm_norm_blocks(p);
         double* parts = chi + (int64_t)nrhs * p->nrings;
-        HIPCHK(launch_alm_norms(p, nrhs, alm, p->d_alm_prev, p->d_alm_r, p->d_alm_y, p->d_mats, parts, s));
+        HIPCHK(launch_alm_norms(p, nrhs, alm, eps ? nullptr : p->d_alm_prev, p->d_alm_r, p->d_alm_y, p->d_mats,
+                                parts, s));
         std::vector<double> hchi((size_t)nrhs * p->nrings), hparts((size_t)nrhs * nb * kNormQ);
         HIPCHK(hipMemcpyAsync(hchi.data(), chi, hchi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hparts.data(), parts, hparts.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -301,7 +365,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
             double c = 0;
             for (int j = 0; j < p->nrings; ++j) c += hchi[(size_t)r * p->nrings + j];
             stats[r].iterations = total;
-            stats[r].cauchy = q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0;
+            stats[r].cauchy = eps ? last_c[r] : (q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0);
             stats[r].residual = q[3] > 0 ? std::sqrt(q[2] / q[3]) : 0.0;
             stats[r].chi2 = c + q[4];
             stats[r].seconds = secs;
@@ -329,6 +393,8 @@ void free_plan(dm_plan* p) {
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
     dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
+    dfree(p->d_cpart); dfree(p->d_cout);
+    if (p->h_cout) (void)hipHostFree(p->h_cout);
     if (p->h_pinned) (void)hipHostFree(p->h_pinned);
     if (p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
@@ -550,6 +616,9 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         dalloc(p, p->d_ninv, 3 * p->npix);
         dalloc(p, p->d_obs, p->npix);
         dalloc(p, p->d_mats, 3 * (size_t)(lmax + 1) * 4);
+        dalloc(p, p->d_cpart, B * (size_t)cauchy_blocks(p) * 2);
+        dalloc(p, p->d_cout, B * 2);
+        HIPCHK(hipHostMalloc((void**)&p->h_cout, B * 2 * sizeof(double), hipHostMallocDefault));
         p->red_len = 64 + B * p->nrings + B * (size_t)alm_norm_blocks(p) * kNormQ + p->nrings;
         dalloc(p, p->d_red, p->red_len);
         HIPCHK(hipStreamSynchronize(p->stream));
@@ -656,10 +725,33 @@ dm_status dm_set_schedule(dm_plan* p, const dm_schedule* sc) {
     return guarded(p, [&] {
         REQUIRE(sc != nullptr, DM_EINVAL, "schedule is null");
         REQUIRE(std::isfinite(sc->lambda_start) && sc->lambda_start >= 1.0, DM_EINVAL, "lambda_start must be >= 1");
-        REQUIRE(sc->nsteps >= 1 && sc->nsteps <= 100000, DM_EINVAL, "nsteps must be in [1, 100000]");
-        REQUIRE(sc->iters_per_step >= 1 && sc->iters_per_step <= 10000000, DM_EINVAL, "iters_per_step must be >= 1");
+        if (sc->iters_per_step >= 1) {
+            REQUIRE(sc->nsteps >= 1 && sc->nsteps <= 100000, DM_EINVAL, "nsteps must be in [1, 100000]");
+            REQUIRE(sc->iters_per_step <= 10000000, DM_EINVAL, "iters_per_step must be <= 1e7");
+        } else {
+            REQUIRE(std::isfinite(sc->beta) && sc->beta > 0.0 && sc->beta < 1.0, DM_EINVAL,
+                    "epsilon mode: beta must be in (0, 1)");
+            REQUIRE(std::isfinite(sc->eps_end) && sc->eps_end > 0.0, DM_EINVAL, "epsilon mode: eps_end must be > 0");
+            REQUIRE(std::isfinite(sc->eps_start) && sc->eps_start >= sc->eps_end, DM_EINVAL,
+                    "epsilon mode: eps_start must be >= eps_end");
+            REQUIRE(std::isfinite(sc->eps_eta) && sc->eps_eta >= 1.0, DM_EINVAL, "epsilon mode: eps_eta must be >= 1");
+            REQUIRE(sc->max_iters >= 1 && sc->max_iters <= 100000000, DM_EINVAL,
+                    "epsilon mode: max_iters must be in [1, 1e8]");
+            REQUIRE(std::log(sc->lambda_start) / -std::log(sc->beta) < 100000.0, DM_EINVAL,
+                    "epsilon mode: more than 1e5 cooling steps");
+        }
         p->sched = *sc;
     });
+}
+
+dm_status dm_schedule_trace(const dm_plan* p, double* cauchy, int* step, int cap, int* n) {
+    if (!p || !n) return DM_EINVAL;
+    const int cnt = (int)p->trace_cauchy.size();
+    const int k = std::max(0, std::min(cap, cnt));
+    if (cauchy) std::copy(p->trace_cauchy.begin(), p->trace_cauchy.begin() + k, cauchy);
+    if (step) std::copy(p->trace_step.begin(), p->trace_step.begin() + k, step);
+    *n = cnt;
+    return DM_OK;
 }
 
 dm_status dm_wiener_filter(dm_plan* p, int nrhs, const double* d, double* alm, double* map, dm_stats* stats) {

@@ -123,7 +123,7 @@ struct dm_plan {
     // spectra / schedule
     bool spectra_set = false;
     std::vector<double> cl;            // [4][lmax+1]
-    dm_schedule sched{1e3, 20, 10};
+    dm_schedule sched{1e3, 20, 10, 0.75, 1e-4, 1e-6, 1.1, 100000};
 
     // work buffers (sized for max_rhs)
     double* d_phase = nullptr;         // [B][3][npairs][mmax+1][2] complex
@@ -143,6 +143,13 @@ struct dm_plan {
     size_t h_pinned_len = 0;
     double* d_red = nullptr;           // reduction scratch
     size_t red_len = 0;
+    // epsilon-mode schedule: Cauchy terms per combine block and per RHS,
+    // their pinned host copy, and the per-iteration record of the last solve
+    double* d_cpart = nullptr;         // [max_rhs][cauchy_blocks][2]
+    double* d_cout = nullptr;          // [max_rhs][2]
+    double* h_cout = nullptr;          // pinned [max_rhs][2]
+    std::vector<double> trace_cauchy;
+    std::vector<int> trace_step;
 
     // timing
     bool profiling = false;
@@ -171,7 +178,9 @@ hipError_t launch_leg_synthesis(dm_plan* p, int nrhs, const double* spin_alm, do
 hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const double* pair_w,
                                double* partial, hipStream_t s);
 hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
-                          double* alm, double* spin, hipStream_t s);
+                          double* alm, double* spin, double* cpart, hipStream_t s);
+int64_t cauchy_blocks(dm_plan* p);   // Cauchy partial sums per RHS written by the combine kernel
+hipError_t launch_cauchy_reduce(dm_plan* p, int nrhs, const double* cpart, double* out, hipStream_t s);
 hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s);
 void set_analysis_tiling(dm_plan* p, int R);
 

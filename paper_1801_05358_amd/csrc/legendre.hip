@@ -499,50 +499,118 @@ __device__ __forceinline__ void eb_to_spin(double2 e, double2 b, double2& p2, do
     m2 = make_double2(-(e.x + b.y), -(e.y - b.x));
 }
 
-__global__ void combine_kernel(int lmax, int64_t nalm, int nchunks, int nrhs, const double2* __restrict__ partial,
-                               const double* __restrict__ filt, double2* __restrict__ alm,
-                               double2* __restrict__ spin) {
+// fixed-order sum of (a, b) over the 256 threads of a combine block into
+// cpart[rhs][block][2]; every thread of the block must call it once
+__device__ void cauchy_block_sum(double a, double b, double* __restrict__ cpart, int nrhs) {
+    __shared__ double sa[256], sb[256];
+    const int t = threadIdx.x;
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sa[t] += sa[t + h];
+            sb[t] += sb[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+        double* o = cpart + ((int64_t)blockIdx.z * nblk + (int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        o[0] = sa[0];
+        o[1] = sb[0];
+    }
+}
+
+// per RHS: fixed-order sum of the combine blocks' Cauchy terms -> out[rhs][2]
+__global__ __launch_bounds__(256) void cauchy_reduce_kernel(const double* __restrict__ cpart, int64_t nblk,
+                                                            double* __restrict__ out) {
+    __shared__ double sa[256], sb[256];
+    const int t = threadIdx.x, rhs = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = t; i < nblk; i += 256) {
+        a += cpart[((int64_t)rhs * nblk + i) * 2];
+        b += cpart[((int64_t)rhs * nblk + i) * 2 + 1];
+    }
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sa[t] += sa[t + h];
+            sb[t] += sb[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[rhs * 2] = sa[0];
+        out[rhs * 2 + 1] = sb[0];
+    }
+}
+
+// cpart (nullable): per-block sums of w |u_new - u_old|^2 and w |u_new|^2
+// over T, E, B (w = 2 for m > 0), the Cauchy ratio's terms; the old value
+// is what alm holds on entry
+__global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, int nchunks, int nrhs,
+                                                      const double2* __restrict__ partial,
+                                                      const double* __restrict__ filt, double2* __restrict__ alm,
+                                                      double2* __restrict__ spin, double* __restrict__ cpart) {
     const int m = blockIdx.y;
     const int rhs = blockIdx.z;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > lmax) return;
-    const int64_t idx = mbase(m, lmax) + l;
-    double2 a[3];
+    double dd = 0.0, nn = 0.0;                         // Cauchy terms of this thread
+    if (l <= lmax) {
+        const int64_t idx = mbase(m, lmax) + l;
+        double2 a[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int c = 0; c < nchunks; ++c) {
-            const double2 v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
-            s.x += v.x;
-            s.y += v.y;
+        for (int f = 0; f < 3; ++f) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int c = 0; c < nchunks; ++c) {
+                const double2 v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
+                s.x += v.x;
+                s.y += v.y;
+            }
+            a[f] = s;
         }
-        a[f] = s;
+        // E = -((2)a + (-2)a)/2,  B = i((2)a - (-2)a)/2
+        double2 E = make_double2(-0.5 * (a[1].x + a[2].x), -0.5 * (a[1].y + a[2].y));
+        double2 B = make_double2(-0.5 * (a[1].y - a[2].y), 0.5 * (a[1].x - a[2].x));
+        if (l < 2) E = B = make_double2(0.0, 0.0);
+        double2 T = a[0];
+        if (filt) {
+            const double ftt = filt[4 * l], fte = filt[4 * l + 1], fee = filt[4 * l + 2], fbb = filt[4 * l + 3];
+            const double2 t2 = make_double2(ftt * T.x + fte * E.x, ftt * T.y + fte * E.y);
+            const double2 e2 = make_double2(fte * T.x + fee * E.x, fte * T.y + fee * E.y);
+            B = make_double2(fbb * B.x, fbb * B.y);
+            T = t2;
+            E = e2;
+        }
+        double2* o = alm + ((int64_t)rhs * 3) * nalm + idx;
+        if (cpart) {
+            const double w = m > 0 ? 2.0 : 1.0;
+            const double2 n3[3] = {T, E, B};
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const double2 old = o[f * nalm];
+                const double dx = n3[f].x - old.x, dy = n3[f].y - old.y;
+                dd += w * (dx * dx + dy * dy);
+                nn += w * (n3[f].x * n3[f].x + n3[f].y * n3[f].y);
+            }
+        }
+        o[0] = T;
+        o[nalm] = E;
+        o[2 * nalm] = B;
+        if (spin) {
+            double2* q = spin + ((int64_t)rhs * 3) * nalm + idx;
+            double2 p2, m2;
+            eb_to_spin(E, B, p2, m2);
+            q[0] = T;
+            q[nalm] = p2;
+            q[2 * nalm] = m2;
+        }
     }
-    // E = -((2)a + (-2)a)/2,  B = i((2)a - (-2)a)/2
-    double2 E = make_double2(-0.5 * (a[1].x + a[2].x), -0.5 * (a[1].y + a[2].y));
-    double2 B = make_double2(-0.5 * (a[1].y - a[2].y), 0.5 * (a[1].x - a[2].x));
-    if (l < 2) E = B = make_double2(0.0, 0.0);
-    double2 T = a[0];
-    if (filt) {
-        const double ftt = filt[4 * l], fte = filt[4 * l + 1], fee = filt[4 * l + 2], fbb = filt[4 * l + 3];
-        const double2 t2 = make_double2(ftt * T.x + fte * E.x, ftt * T.y + fte * E.y);
-        const double2 e2 = make_double2(fte * T.x + fee * E.x, fte * T.y + fee * E.y);
-        B = make_double2(fbb * B.x, fbb * B.y);
-        T = t2;
-        E = e2;
-    }
-    double2* o = alm + ((int64_t)rhs * 3) * nalm + idx;
-    o[0] = T;
-    o[nalm] = E;
-    o[2 * nalm] = B;
-    if (spin) {
-        double2* q = spin + ((int64_t)rhs * 3) * nalm + idx;
-        double2 p2, m2;
-        eb_to_spin(E, B, p2, m2);
-        q[0] = T;
-        q[nalm] = p2;
-        q[2 * nalm] = m2;
-    }
+    // cpart is uniform over the grid, so the whole block takes this branch
+    if (cpart) cauchy_block_sum(dd, nn, cpart, nrhs);
 }
 
 // (T, E, B) -> (T, (2)a, (-2)a)
@@ -608,11 +676,18 @@ void set_analysis_tiling(dm_plan* p, int R) {
 }
 
 hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
-                          double* alm, double* spin, hipStream_t s) {
+                          double* alm, double* spin, double* cpart, hipStream_t s) {
     dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
     hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
                        reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
-                       reinterpret_cast<double2*>(spin));
+                       reinterpret_cast<double2*>(spin), cpart);
+    return hipGetLastError();
+}
+
+int64_t cauchy_blocks(dm_plan* p) { return (int64_t)((p->lmax + 1 + 255) / 256) * (p->mmax + 1); }
+
+hipError_t launch_cauchy_reduce(dm_plan* p, int nrhs, const double* cpart, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(cauchy_reduce_kernel, dim3(nrhs), dim3(256), 0, s, cpart, cauchy_blocks(p), out);
     return hipGetLastError();
 }
 

@@ -33,7 +33,9 @@ class DmGrid(ctypes.Structure):
 
 
 class DmSchedule(ctypes.Structure):
-    _fields_ = [("lambda_start", ctypes.c_double), ("nsteps", ctypes.c_int), ("iters_per_step", ctypes.c_int)]
+    _fields_ = [("lambda_start", ctypes.c_double), ("nsteps", ctypes.c_int), ("iters_per_step", ctypes.c_int),
+                ("beta", ctypes.c_double), ("eps_start", ctypes.c_double), ("eps_end", ctypes.c_double),
+                ("eps_eta", ctypes.c_double), ("max_iters", ctypes.c_int)]
 
 
 class DmStats(ctypes.Structure):
@@ -74,6 +76,8 @@ def lib():
         "dm_set_spectra": (ctypes.c_int, [_P, _D]),
         "dm_set_noise": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]),
         "dm_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(DmSchedule)]),
+        "dm_schedule_trace": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_int)]),
         "dm_wiener_filter": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, ctypes.POINTER(DmStats)]),
         "dm_wiener_filter_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
         "dm_constrained_realizations": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, _D, _D]),
@@ -98,7 +102,8 @@ def lib():
 def exported_symbols():
     """Names declared in include/dmwf.h that the binding expects."""
     return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
-            "dm_set_spectra", "dm_set_noise", "dm_set_schedule", "dm_wiener_filter", "dm_wiener_filter_device",
+            "dm_set_spectra", "dm_set_noise", "dm_set_schedule", "dm_schedule_trace", "dm_wiener_filter",
+            "dm_wiener_filter_device",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
             "dm_map2alm_device", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
 
@@ -177,8 +182,27 @@ class Plan:
         self._check(lib().dm_set_noise(self._h, _dptr(ncov), NCOV_DIAG3, optr))
 
     def set_schedule(self, lambda_start=1e3, nsteps=20, iters_per_step=10):
-        s = DmSchedule(float(lambda_start), int(nsteps), int(iters_per_step))
+        """Fixed mode: nsteps cooling steps lambda_start -> 1, iters_per_step each."""
+        s = DmSchedule(float(lambda_start), int(nsteps), int(iters_per_step), 0.0, 0.0, 0.0, 0.0, 0)
         self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
+
+    def set_schedule_eps(self, lambda_start=1e3, beta=0.75, eps_start=1e-4, eps_end=1e-6, eta=1.1,
+                         max_iters=100000):
+        """Epsilon mode (Algorithm 1's stopping rule with the cooled threshold)."""
+        s = DmSchedule(float(lambda_start), 0, 0, float(beta), float(eps_start), float(eps_end), float(eta),
+                       int(max_iters))
+        self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
+
+    def schedule_trace(self):
+        """(cauchy [n], step [n]) of the last epsilon-mode solve."""
+        n = ctypes.c_int(0)
+        self._check(lib().dm_schedule_trace(self._h, None, None, 0, ctypes.byref(n)))
+        c = np.zeros(n.value)
+        st = np.zeros(n.value, dtype=np.int32)
+        self._check(lib().dm_schedule_trace(self._h, c.ctypes.data_as(_D),
+                                            st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n.value,
+                                            ctypes.byref(n)))
+        return c, st
 
     # -- solves ------------------------------------------------------------
     def wiener_filter(self, d, want_map=False, want_stats=False):

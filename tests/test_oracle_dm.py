@@ -194,3 +194,73 @@ def test_linearity_for_constrained_realizations():
     wd = dm.solve(sht, d, ncov, obs, cl, 1e3, 3, 5)["u"]
     wdh = dm.solve(sht, dhat, ncov, obs, cl, 1e3, 3, 5)["u"]
     assert rel(scr, wd + (shat - wdh), lmax) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# the epsilon-driven schedule (Algorithm 1's stopping rule, Sec. 3.2)
+# ----------------------------------------------------------------------------
+def test_eps_schedule_is_geometric_down_to_one():
+    lam = dm.eps_schedule(1e3, 0.75)
+    assert lam[0] == 1e3 and lam[-1] == 1.0
+    assert np.all(lam[:-1] > 1.0)
+    assert np.allclose(lam[1:-1] / lam[:-2], 0.75, rtol=1e-15, atol=0)
+    # the last geometric value is the first one not above 1 times 1/beta
+    assert lam[-2] * 0.75 <= 1.0
+    assert np.array_equal(dm.eps_schedule(1.0, 0.5), [1.0])
+    assert np.array_equal(dm.eps_schedule(16.0, 0.5), [16.0, 8.0, 4.0, 2.0, 1.0])
+
+
+def test_eps_thresholds_cool_by_eta_with_floor():
+    eps = dm.eps_thresholds(30, 1e-4, 1e-6, 1.1)
+    assert eps[0] == 1e-4 and eps[-1] == 1e-6
+    assert np.all(np.diff(eps) <= 0)
+    assert np.isclose(eps[1], 1e-4 / 1.1, rtol=1e-15)
+    # the floor: 1e-4 / 1.1^j reaches 1e-6 at j = 49 (beyond 30 steps, so
+    # only the last entry is at the floor here)
+    assert np.all(eps[:-1] > 1e-6)
+    long = dm.eps_thresholds(60, 1e-4, 1e-6, 1.1)
+    assert np.all(long[49:] == 1e-6) and long[48] > 1e-6
+
+
+def test_eps_mode_with_loose_threshold_is_one_iteration_per_step():
+    """With thresholds above any Cauchy ratio every step stops after one
+    iteration, which is the fixed schedule with one iteration per step over
+    the same lambdas (16 -> 1 by halving = 16^(1 - k/4))."""
+    lmax = 6
+    sht, cl, ncov, obs, d = small_problem(gl_grid(lmax + 1, 2 * lmax + 1), lmax, seed=21)
+    r = dm.solve_eps(sht, d, ncov, obs, cl, 16.0, 0.5, 10.0, 10.0, 1.0, 1000)
+    ref = dm.solve(sht, d, ncov, obs, cl, 16.0, 5, 1)
+    assert r["iterations"] == 5 and r["steps"] == [0, 1, 2, 3, 4]
+    assert r["trace"][0] == 1.0                         # u_0 = 0
+    assert rel(r["u"], ref["u"], lmax) < 1e-13
+
+
+def test_eps_mode_iteration_cap():
+    """A threshold of zero never stops a step: the cap ends the solve, and
+    at lambda = 1 that is the fixed schedule with the cap's iteration count."""
+    lmax = 6
+    sht, cl, ncov, obs, d = small_problem(gl_grid(lmax + 1, 2 * lmax + 1), lmax, seed=22)
+    r = dm.solve_eps(sht, d, ncov, obs, cl, 1.0, 0.5, 0.0, 0.0, 1.0, 7)
+    ref = dm.solve(sht, d, ncov, obs, cl, 1.0, 1, 7)
+    assert r["iterations"] == 7 and set(r["steps"]) == {0}
+    assert rel(r["u"], ref["u"], lmax) < 1e-13
+
+
+def test_eps_mode_converges_to_exact_wiener_filter_on_gl():
+    """On an exact-quadrature grid the stopping rule with a tight final
+    threshold ends at the exact WF (eq 2); every step ends below its
+    threshold, and the Cauchy ratio of each step's first iteration after
+    cooling is larger than the last one of the step before (the peaks of
+    Fig. 4)."""
+    lmax = 6
+    sht, cl, ncov, obs, d = small_problem(gl_grid(lmax + 1, 2 * lmax + 1), lmax, seed=23)
+    r = dm.solve_eps(sht, d, ncov, obs, cl, 1e3, 0.75, 1e-4, 1e-12, 1.1, 100000)
+    wf = dense.wiener_filter(sht, d, ncov, obs, cl)
+    assert r["iterations"] < 100000
+    assert r["trace"][-1] < 1e-12
+    assert rel(r["u"], wf, lmax) < 1e-9
+    tr, st = np.array(r["trace"]), np.array(r["steps"])
+    for j in range(len(r["lambdas"])):
+        assert tr[st == j][-1] < r["eps"][j]
+    firsts = [np.flatnonzero(st == j)[0] for j in range(1, len(r["lambdas"]))]
+    assert all(tr[i] > tr[i - 1] for i in firsts)
