@@ -112,10 +112,16 @@ void collect_events(dm_plan* p) {
 // --------------------------------------------------------------------------
 // transform building blocks
 // --------------------------------------------------------------------------
-void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const double* b, double* phase,
-          hipStream_t s) {
+// ring Fourier data of the plan's current precision: FP32 storage for the
+// mixed transforms (their products round the data to FP32 anyway), FP64
+// otherwise (also for a mixed plan's FP64 epilogue)
+void* phase_of(dm_plan* p) {
+    return (p->precision == DM_MIXED && p->d_phase32) ? (void*)p->d_phase32 : (void*)p->d_phase;
+}
+
+void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const double* b, hipStream_t s) {
     Timed t(p, KC_RING, s);
-    HIPCHK(launch_ring(p, mode, nrhs, in, out, p->d_K, b, phase, s));
+    HIPCHK(launch_ring(p, mode, nrhs, in, out, p->d_K, b, phase_of(p), s));
     t.done();
 }
 
@@ -129,8 +135,9 @@ bool use_mfma(dm_plan* p, int nrhs) {
     return nrhs >= 8;
 }
 
-void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, const double* filter, double* alm,
-                  double* spin, hipStream_t s, double* cpart = nullptr) {
+void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, double* alm, double* spin,
+                  hipStream_t s, double* cpart = nullptr) {
+    const void* phase = phase_of(p);
     const double* w = weighted ? p->d_pair_w : p->d_pair_one;
     int nslots = p->ana_chunks;
     {
@@ -140,7 +147,7 @@ void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, cons
             nslots = batched_analysis_slots(p);
             HIPCHK(launch_bana(p, nrhs, phase, w, p->d_partial, s));
         } else {
-            HIPCHK(launch_leg_analysis(p, nrhs, phase, w, p->d_partial, s));
+            HIPCHK(launch_leg_analysis(p, nrhs, static_cast<const double*>(phase), w, p->d_partial, s));
         }
         t.done();
     }
@@ -150,27 +157,28 @@ void leg_analysis(dm_plan* p, int nrhs, const double* phase, bool weighted, cons
 }
 
 // synthesis from spin-basis coefficients
-void leg_synthesis(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
+void leg_synthesis(dm_plan* p, int nrhs, const double* spin, hipStream_t s) {
+    void* phase = phase_of(p);
     Timed t(p, KC_LEG_SYNTHESIS, s);
     if (use_mfma(p, nrhs)) {
         p->mfma_nct = 1;
         HIPCHK(launch_bsyn(p, nrhs, spin, phase, s));
     } else {
-        HIPCHK(launch_leg_synthesis(p, nrhs, spin, phase, s));
+        HIPCHK(launch_leg_synthesis(p, nrhs, spin, static_cast<double*>(phase), s));
     }
     t.done();
 }
 
 // map (device) -> alm (device): A = Y^T W (weighted) or Y^T
 void map2alm_dev(dm_plan* p, int nrhs, const double* map, double* alm, bool weighted, hipStream_t s) {
-    ring(p, RING_ANALYSIS, nrhs, map, nullptr, nullptr, p->d_phase, s);
-    leg_analysis(p, nrhs, p->d_phase, weighted, nullptr, alm, nullptr, s);
+    ring(p, RING_ANALYSIS, nrhs, map, nullptr, nullptr, s);
+    leg_analysis(p, nrhs, weighted, nullptr, alm, nullptr, s);
 }
 
 void alm2map_dev(dm_plan* p, int nrhs, const double* alm, double* map, hipStream_t s) {
     HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, s));
-    leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
-    ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, p->d_phase, s);
+    leg_synthesis(p, nrhs, p->d_alm_spin, s);
+    ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, s);
 }
 
 // runs the transforms of a scope in another precision (the mixed plan's
@@ -252,7 +260,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
 
     // setup: d0 = mask(d), b = T N^-1 d0, t_0 = d0
     HIPCHK(launch_data_setup(p, nrhs, d, p->d_d0, p->d_b, s));
-    ring(p, RING_ANALYSIS, nrhs, p->d_d0, nullptr, nullptr, p->d_phase, s);
+    ring(p, RING_ANALYSIS, nrhs, p->d_d0, nullptr, nullptr, s);
     const int nsteps = (int)lam.size();
     const bool eps = eps_mode(p->sched);
     p->trace_cauchy.clear();
@@ -270,14 +278,14 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 if (last && stats) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_len * sizeof(double),
                                                          hipMemcpyDeviceToDevice, s));
                 // t_hat = A t ; u = F t_hat        (eq 8)
-                leg_analysis(p, nrhs, p->d_phase, true, F, alm, p->d_alm_spin, s);
+                leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
                 // u_x = Y u                          (synthesis)
-                leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
+                leg_synthesis(p, nrhs, p->d_alm_spin, s);
                 if (!last) {
                     // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
-                    ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, p->d_phase, s);
+                    ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, s);
                 } else {
-                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
+                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
                 }
             }
         }
@@ -300,12 +308,12 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
             const double thr = (k == nsteps - 1) ? sc.eps_end
                                                  : std::max(sc.eps_end, sc.eps_start * std::pow(sc.eps_eta, -(double)k));
             for (;;) {
-                leg_analysis(p, nrhs, p->d_phase, true, F, alm, p->d_alm_spin, s, p->d_cpart);
+                leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s, p->d_cpart);
                 HIPCHK(launch_cauchy_reduce(p, nrhs, p->d_cpart, p->d_cout, s));
                 HIPCHK(hipMemcpyAsync(p->h_cout, p->d_cout, (size_t)nrhs * 2 * sizeof(double), hipMemcpyDeviceToHost,
                                       s));
                 HIPCHK(hipEventRecord(ev.e, s));
-                leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, s);
+                leg_synthesis(p, nrhs, p->d_alm_spin, s);
                 HIPCHK(hipEventSynchronize(ev.e));
                 double c = 0.0;
                 for (int r = 0; r < nrhs; ++r) {
@@ -319,11 +327,11 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 ++total;
                 const bool conv = c < thr;
                 if ((conv && k == nsteps - 1) || total >= sc.max_iters) {
-                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, p->d_phase, s);
+                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
                     done = true;
                     break;
                 }
-                ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, p->d_phase, s);
+                ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, s);
                 if (conv) break;
             }
         }
@@ -390,7 +398,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
     dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
-    dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_partial);
+    dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
     dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
     dfree(p->d_cpart); dfree(p->d_cout);
@@ -593,6 +601,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         // work buffers
         const size_t B = (size_t)max_rhs;
         dalloc(p, p->d_phase, B * 3 * p->npairs * (p->mmax + 1) * 4);
+        if (precision == DM_MIXED) dalloc(p, p->d_phase32, B * 3 * p->npairs * (p->mmax + 1) * 4);
         // partial-sum slots for every kernel the plan may run (a mixed plan
         // also runs the FP64 batched kernels for its FP64 epilogue)
         size_t slots = (size_t)std::max(p->ana_chunks, batched_analysis_slots(p));
@@ -910,11 +919,11 @@ dm_status dm_iterate(dm_plan* p, int nrhs, const double* d, const double* t_in, 
         upload(p, dd, d, nm);
         upload(p, dt, t_in, nm);
         HIPCHK(launch_data_setup(p, nrhs, dd, p->d_d0, p->d_b, p->stream));
-        ring(p, RING_ANALYSIS, nrhs, dt, nullptr, nullptr, p->d_phase, p->stream);
+        ring(p, RING_ANALYSIS, nrhs, dt, nullptr, nullptr, p->stream);
         for (int i = 0; i < niter; ++i) {
-            leg_analysis(p, nrhs, p->d_phase, true, p->d_filters, p->d_alm, p->d_alm_spin, p->stream);
-            leg_synthesis(p, nrhs, p->d_alm_spin, p->d_phase, p->stream);
-            ring(p, RING_ITERATE, nrhs, nullptr, (i == niter - 1) ? dt : nullptr, p->d_b, p->d_phase, p->stream);
+            leg_analysis(p, nrhs, true, p->d_filters, p->d_alm, p->d_alm_spin, p->stream);
+            leg_synthesis(p, nrhs, p->d_alm_spin, p->stream);
+            ring(p, RING_ITERATE, nrhs, nullptr, (i == niter - 1) ? dt : nullptr, p->d_b, p->stream);
         }
         HIPCHK(hipMemcpyAsync(alm, p->d_alm, na * sizeof(double), hipMemcpyDeviceToHost, p->stream));
         if (t_out) HIPCHK(hipMemcpyAsync(t_out, dt, nm * sizeof(double), hipMemcpyDeviceToHost, p->stream));

@@ -127,6 +127,7 @@ struct dm_plan {
 
     // work buffers (sized for max_rhs)
     double* d_phase = nullptr;         // [B][3][npairs][mmax+1][2] complex
+    float* d_phase32 = nullptr;        // the same in FP32, for the mixed transforms
     double* d_partial = nullptr;       // [chunks][B][3][nalm] complex
     double* d_alm = nullptr;           // [B][3][nalm] complex
     double* d_alm_prev = nullptr;      // [B][3][nalm] complex
@@ -188,8 +189,9 @@ void set_analysis_tiling(dm_plan* p, int R);
 // (FP64 for DM_FP64 plans, FP32 for DM_MIXED); analysis writes one
 // partial-sum slot per block of ring pairs
 int batched_analysis_slots(dm_plan* p);
-hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s);
-hipError_t launch_bana(dm_plan* p, int nrhs, const double* phase, const double* pair_w, double* partial,
+// batched kernels: phase is FP32 ring data for DM_MIXED, FP64 otherwise
+hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, void* phase, hipStream_t s);
+hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pair_w, double* partial,
                        hipStream_t s);
 
 // ringfft.hip
@@ -197,8 +199,9 @@ enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3 };
 // RING_ANALYSIS: map -> phase.  RING_SYNTH: phase -> map.
 // RING_ITERATE: phase -> (K x + b) -> phase.
 // RING_ITERATE with map_out != null also stores the updated messenger t.
+// phase: FP32 ring data for DM_MIXED plans, FP64 otherwise
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out,
-                       const double* K, const double* b, double* phase, hipStream_t s);
+                       const double* K, const double* b, void* phase, hipStream_t s);
 hipError_t ring_set_lds_limit(size_t bytes);
 
 // pointwise.hip

@@ -49,6 +49,28 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// complex values of the ring Fourier data, stored in the kernel's own
+// precision (FP32 ring data for the mixed plans: the products round it to
+// FP32 anyway)
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    typedef float2 t;
+};
+template <>
+struct Vec2<double> {
+    typedef double2 t;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::t vec2(double x, double y) {
+    typename Vec2<T>::t v;
+    v.x = (T)x;
+    v.y = (T)y;
+    return v;
+}
+
 __device__ __forceinline__ int64_t mbase(int m, int lmax) { return (int64_t)m * (2 * lmax + 1 - m) / 2; }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -257,7 +279,7 @@ __device__ __forceinline__ void bsyn_mfma(const SynTile<T, PW>& tl, int k, int r
 
 template <typename T, int PW>
 __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const double2* __restrict__ spin,
-                                                              double* __restrict__ phase) {
+                                                              T* __restrict__ phase) {
     typedef typename Mfma<T>::v4 v4;
     constexpr int NT = PW / 16;                       // row tiles per side
     constexpr int WB = syn_wave_bytes<T, PW>();
@@ -381,7 +403,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     // U = (P - M)/(2i) and writes 32 contiguous bytes (both sides, re/im)
     // per field
     T* stg = reinterpret_cast<T*>(&lds[wv][0]);
-    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 4;     // doubles per field
+    const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 4;     // values per field
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         wave_sync();
@@ -413,16 +435,17 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
                     uv[2 * sd] = 0.5 * (pi - mi);
                     uv[2 * sd + 1] = -0.5 * (pr - mr);
                 }
-                double2* o = reinterpret_cast<double2*>(
-                    phase + ((((int64_t)rw * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 4);
-                o[0] = double2{(double)g[0], (double)g[1]};
-                o[1] = double2{(double)g[2], (double)g[3]};
-                double2* oq = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + fstride);
-                oq[0] = double2{qv[0], qv[1]};
-                oq[1] = double2{qv[2], qv[3]};
-                double2* ou = reinterpret_cast<double2*>(reinterpret_cast<double*>(o) + 2 * fstride);
-                ou[0] = double2{uv[0], uv[1]};
-                ou[1] = double2{uv[2], uv[3]};
+                typedef typename Vec2<T>::t T2;
+                T* ob = phase + ((((int64_t)rw * 3) * A.npairs + pair) * (A.mmax + 1) + m) * 4;
+                T2* o = reinterpret_cast<T2*>(ob);
+                o[0] = vec2<T>(g[0], g[1]);
+                o[1] = vec2<T>(g[2], g[3]);
+                T2* oq = reinterpret_cast<T2*>(ob + fstride);
+                oq[0] = vec2<T>(qv[0], qv[1]);
+                oq[1] = vec2<T>(qv[2], qv[3]);
+                T2* ou = reinterpret_cast<T2*>(ob + 2 * fstride);
+                ou[0] = vec2<T>(uv[0], uv[1]);
+                ou[1] = vec2<T>(uv[2], uv[3]);
             }
         }
     }
@@ -459,7 +482,7 @@ __device__ __forceinline__ void rec_act(const BatchArgs& A, const double* __rest
 }
 
 template <typename T, int W>
-__global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2* __restrict__ phase,
+__global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typename Vec2<T>::t* __restrict__ phase,
                                                       const double* __restrict__ pair_w,
                                                       double* __restrict__ partial) {
     typedef typename Mfma<T>::v4 v4;
@@ -499,8 +522,9 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const double2
         const bool ok = pair < A.npairs && rhs_ok;
         const int pc = ok ? pair : 0;
         const double w = pair_w[pc];
-        const double2* in = phase + ((((int64_t)(rhs_ok ? rhs : 0) * 3) * A.npairs + pc) * (A.mmax + 1) + m) * 2 + sd;
-        const double2 t0 = in[0], q0 = in[fstride], u0 = in[2 * fstride];
+        const typename Vec2<T>::t* in =
+            phase + ((((int64_t)(rhs_ok ? rhs : 0) * 3) * A.npairs + pc) * (A.mmax + 1) + m) * 2 + sd;
+        const typename Vec2<T>::t t0 = in[0], q0 = in[fstride], u0 = in[2 * fstride];
         const double gt = ri ? t0.y : t0.x;
         const double gp = ri ? (q0.y + u0.x) : (q0.x - u0.y);
         const double gm = ri ? (q0.y - u0.x) : (q0.x + u0.y);
@@ -681,7 +705,7 @@ int batched_analysis_slots(dm_plan* p) {
     return (p->npairs + per - 1) / per;
 }
 
-hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, hipStream_t s) {
+hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, void* phase, hipStream_t s) {
     BatchArgs A = batch_args(p, nrhs);
     const int pw = p->precision == DM_MIXED ? 64 : 32;
     A.nx = (p->npairs + pw * kSynWaves - 1) / (pw * kSynWaves);
@@ -689,23 +713,25 @@ hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, double* phase, 
     dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
     dim3 block(64 * kSynWaves);
     const double2* sp = reinterpret_cast<const double2*>(spin);
-    if (p->precision == DM_MIXED) hipLaunchKernelGGL((bsyn_kernel<float, 64>), grid, block, 0, s, A, sp, phase);
-    else hipLaunchKernelGGL((bsyn_kernel<double, 32>), grid, block, 0, s, A, sp, phase);
+    if (p->precision == DM_MIXED)
+        hipLaunchKernelGGL((bsyn_kernel<float, 64>), grid, block, 0, s, A, sp, static_cast<float*>(phase));
+    else
+        hipLaunchKernelGGL((bsyn_kernel<double, 32>), grid, block, 0, s, A, sp, static_cast<double*>(phase));
     return hipGetLastError();
 }
 
-hipError_t launch_bana(dm_plan* p, int nrhs, const double* phase, const double* pair_w, double* partial,
+hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pair_w, double* partial,
                        hipStream_t s) {
     BatchArgs A = batch_args(p, nrhs);
     A.nx = batched_analysis_slots(p);
     A.mchunk = p->ana_mchunk;
     dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
-    const double2* ph = reinterpret_cast<const double2*>(phase);
     if (p->precision == DM_MIXED)
-        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves>), grid, dim3(64 * kAnaWaves), 0, s, A, ph, pair_w, partial);
+        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves>), grid, dim3(64 * kAnaWaves), 0, s, A,
+                           static_cast<const float2*>(phase), pair_w, partial);
     else
-        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves / 2>), grid, dim3(32 * kAnaWaves), 0, s, A, ph, pair_w,
-                           partial);
+        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves / 2>), grid, dim3(32 * kAnaWaves), 0, s, A,
+                           static_cast<const double2*>(phase), pair_w, partial);
     return hipGetLastError();
 }
 

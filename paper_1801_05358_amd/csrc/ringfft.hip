@@ -197,18 +197,19 @@ __device__ void idft_core(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A) 
     }
 }
 
-template <int MODE, typename R>
+template <int MODE, typename R, typename P>
 __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* __restrict__ map_in,
                                                    double* __restrict__ map_out, const double* __restrict__ Kp,
-                                                   const double* __restrict__ bp, double2* __restrict__ phase) {
+                                                   const double* __restrict__ bp, C2<P>* __restrict__ phase) {
     typedef C2<R> CR;
+    typedef C2<P> CP;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     CR* buf = reinterpret_cast<CR*>(lds_raw);
     const int p = blockIdx.x;
     const int rhs = blockIdx.y;
-    const RingPairDev P = A.pairs[p];
-    const FftLenDev L = A.lens[P.len_idx];
-    const int n = P.nphi, M = L.M, logM = L.logM;
+    const RingPairDev P_ = A.pairs[p];
+    const FftLenDev L = A.lens[P_.len_idx];
+    const int n = P_.nphi, M = L.M, logM = L.logM;
     const int nt = blockDim.x, tid = threadIdx.x;
     const int mmax = A.mmax;
     const bool synth = (MODE == RING_SYNTH || MODE == RING_ITERATE);
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
     const CR zero = mk<R>(0, 0);
 
     for (int f = 0; f < 3; ++f) {
-        double2* ph = phase + (((int64_t)rhs * 3 + f) * A.npairs + p) * (mmax + 1) * 2;
+        CP* ph = phase + (((int64_t)rhs * 3 + f) * A.npairs + p) * (mmax + 1) * 2;
         const int64_t moff = ((int64_t)rhs * 3 + f) * A.npix;
         if (synth) {
             // fold into n bins, place conj(C_N + i C_S) for the inverse transform
@@ -229,10 +230,10 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                     const int mstart = j - n * ((j + mmax) / n);
                     for (int m = mstart; m <= mmax; m += n) {
                         const int a = m < 0 ? -m : m;
-                        const double2 fnd = ph[2 * a], fsd = ph[2 * a + 1];
+                        const CP fnd = ph[2 * a], fsd = ph[2 * a + 1];
                         CR fn = mk<R>((R)fnd.x, (R)fnd.y), fs = mk<R>((R)fsd.x, (R)fsd.y);
                         if (m < 0) { fn.y = -fn.y; fs.y = -fs.y; }
-                        const CR rot = phase_rot<R>(m, P.phi0_den);
+                        const CR rot = phase_rot<R>(m, P_.phi0_den);
                         const CR tn = cmul(fn, rot), ts = cmul(fs, rot);
                         cn.x += tn.x; cn.y += tn.y;
                         cs.x += ts.x; cs.y += ts.y;
@@ -252,19 +253,19 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                 if (L.bluestein) y = cmul(y, chirp[j]);
                 const double xn = (double)y.x, xs = -(double)y.y;
                 if (MODE == RING_SYNTH) {
-                    map_out[moff + P.off_n + j] = xn;
-                    if (P.has_s) map_out[moff + P.off_s + j] = xs;
+                    map_out[moff + P_.off_n + j] = xn;
+                    if (P_.has_s) map_out[moff + P_.off_s + j] = xs;
                 } else {
-                    const int64_t kn = (int64_t)f * A.npix + P.off_n + j;
-                    double tn = Kp[kn] * xn + bp[moff + P.off_n + j];
+                    const int64_t kn = (int64_t)f * A.npix + P_.off_n + j;
+                    double tn = Kp[kn] * xn + bp[moff + P_.off_n + j];
                     double ts = 0.0;
-                    if (P.has_s) {
-                        const int64_t ks = (int64_t)f * A.npix + P.off_s + j;
-                        ts = Kp[ks] * xs + bp[moff + P.off_s + j];
+                    if (P_.has_s) {
+                        const int64_t ks = (int64_t)f * A.npix + P_.off_s + j;
+                        ts = Kp[ks] * xs + bp[moff + P_.off_s + j];
                     }
                     if (map_out) {
-                        map_out[moff + P.off_n + j] = tn;
-                        if (P.has_s) map_out[moff + P.off_s + j] = ts;
+                        map_out[moff + P_.off_n + j] = tn;
+                        if (P_.has_s) map_out[moff + P_.off_s + j] = ts;
                     }
                     CR a = mk<R>((R)tn, (R)ts);
                     if (L.bluestein) a = cmul(a, chirp[j]);
@@ -281,8 +282,8 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                 const int j = (int)brev(q, logM);
                 CR a = zero;
                 if (j < n) {
-                    a.x = (R)map_in[moff + P.off_n + j];
-                    a.y = P.has_s ? (R)map_in[moff + P.off_s + j] : R(0);
+                    a.x = (R)map_in[moff + P_.off_n + j];
+                    a.y = P_.has_s ? (R)map_in[moff + P_.off_s + j] : R(0);
                     if (L.bluestein) a = cmul(a, chirp[j]);
                 }
                 buf[pidx(q)] = a;
@@ -301,10 +302,10 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                 // X_N = (Z_k + conj Z_{-k}) / 2,  X_S = (Z_k - conj Z_{-k}) / (2i)
                 const CR xn = mk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
                 const CR xs = mk<R>(R(0.5) * (z1.y + z2.y), R(-0.5) * (z1.x - z2.x));
-                const CR rot = conjc(phase_rot<R>(m, P.phi0_den));
+                const CR rot = conjc(phase_rot<R>(m, P_.phi0_den));
                 const CR on = cmul(xn, rot), os = cmul(xs, rot);
-                ph[2 * m] = make_double2((double)on.x, (double)on.y);
-                ph[2 * m + 1] = P.has_s ? make_double2((double)os.x, (double)os.y) : make_double2(0.0, 0.0);
+                ph[2 * m] = mk<P>((P)on.x, (P)on.y);
+                ph[2 * m + 1] = P_.has_s ? mk<P>((P)os.x, (P)os.y) : mk<P>(0, 0);
             }
             __syncthreads();
         }
@@ -328,35 +329,36 @@ RingArgs<R> ring_args(dm_plan* p, const void* chirp, const void* bhat, const voi
     return A;
 }
 
-template <typename R>
+template <typename R, typename P>
 void launch_ring_t(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
-                   const double* b, double2* ph, const RingArgs<R>& A, hipStream_t s) {
+                   const double* b, void* phase, const RingArgs<R>& A, hipStream_t s) {
+    C2<P>* ph = static_cast<C2<P>*>(phase);
     dim3 grid(p->npairs, nrhs);
     dim3 block(p->fft_threads);
     const size_t lds = (size_t)(p->fft.Mmax + p->fft.Mmax / 8) * sizeof(C2<R>);
     switch (mode) {
         case RING_ANALYSIS:
-            hipLaunchKernelGGL((ring_kernel<RING_ANALYSIS, R>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
+            hipLaunchKernelGGL((ring_kernel<RING_ANALYSIS, R, P>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
             break;
         case RING_SYNTH:
-            hipLaunchKernelGGL((ring_kernel<RING_SYNTH, R>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
+            hipLaunchKernelGGL((ring_kernel<RING_SYNTH, R, P>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
             break;
         default:
-            hipLaunchKernelGGL((ring_kernel<RING_ITERATE, R>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
+            hipLaunchKernelGGL((ring_kernel<RING_ITERATE, R, P>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
             break;
     }
 }
 
-template <typename R>
+template <typename R, typename P>
 hipError_t set_lds_t(size_t bytes) {
     hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_ANALYSIS, R>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_ANALYSIS, R, P>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_SYNTH, R>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_SYNTH, R, P>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_ITERATE, R>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_ITERATE, R, P>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -365,22 +367,26 @@ hipError_t set_lds_t(size_t bytes) {
 // FP32 transforms for mixed plans that carry the FP32 tables (opt-in at
 // plan creation), FP64 otherwise
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
-                       const double* b, double* phase, hipStream_t s) {
-    double2* ph = reinterpret_cast<double2*>(phase);
-    if (p->precision == DM_MIXED && p->d_tw32) {
+                       const double* b, void* phase, hipStream_t s) {
+    if (p->precision != DM_MIXED) {
+        const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw);
+        launch_ring_t<double, double>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
+    } else if (p->d_tw32) {
         const RingArgs<float> A = ring_args<float>(p, p->d_chirp32, p->d_bhat32, p->d_tw32);
-        launch_ring_t<float>(p, mode, nrhs, map_in, map_out, K, b, ph, A, s);
+        launch_ring_t<float, float>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
     } else {
         const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw);
-        launch_ring_t<double>(p, mode, nrhs, map_in, map_out, K, b, ph, A, s);
+        launch_ring_t<double, float>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
     }
     return hipGetLastError();
 }
 
 hipError_t ring_set_lds_limit(size_t bytes) {
-    hipError_t e = set_lds_t<double>(bytes);
+    hipError_t e = set_lds_t<double, double>(bytes);
     if (e != hipSuccess) return e;
-    return set_lds_t<float>(bytes / 2);
+    e = set_lds_t<double, float>(bytes);
+    if (e != hipSuccess) return e;
+    return set_lds_t<float, float>(bytes / 2);
 }
 
 }  // namespace dmwf
