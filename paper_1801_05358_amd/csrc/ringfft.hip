@@ -47,7 +47,7 @@ __device__ __forceinline__ C2<R> mk(R x, R y) {
 
 template <typename R>
 struct RingArgs {
-    int npairs, mmax, logMmax;
+    int npairs, mmax, logMmax, nrhs;
     int64_t npix;
     const RingPairDev* __restrict__ pairs;
     const FftLenDev* __restrict__ lens;
@@ -205,8 +205,13 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
     typedef C2<P> CP;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     CR* buf = reinterpret_cast<CR*>(lds_raw);
-    const int p = blockIdx.x;
-    const int rhs = blockIdx.y;
+    // workgroups go to the 8 XCDs in turn: the RHS of one ring pair are
+    // placed consecutively on one XCD, so that they share that ring's
+    // tables (chirp, Bluestein kernel, K) in its L2
+    const int c = blockIdx.x % 8, k = blockIdx.x / 8;
+    const int rhs = k % A.nrhs;
+    const int p = 8 * (k / A.nrhs) + c;
+    if (p >= A.npairs) return;
     const RingPairDev P_ = A.pairs[p];
     const FftLenDev L = A.lens[P_.len_idx];
     const int n = P_.nphi, M = L.M, logM = L.logM;
@@ -333,18 +338,20 @@ template <typename R, typename P>
 void launch_ring_t(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
                    const double* b, void* phase, const RingArgs<R>& A, hipStream_t s) {
     C2<P>* ph = static_cast<C2<P>*>(phase);
-    dim3 grid(p->npairs, nrhs);
+    RingArgs<R> Ar = A;
+    Ar.nrhs = nrhs;
+    dim3 grid((unsigned)(((p->npairs + 7) / 8) * 8 * nrhs));
     dim3 block(p->fft_threads);
     const size_t lds = (size_t)(p->fft.Mmax + p->fft.Mmax / 8) * sizeof(C2<R>);
     switch (mode) {
         case RING_ANALYSIS:
-            hipLaunchKernelGGL((ring_kernel<RING_ANALYSIS, R, P>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
+            hipLaunchKernelGGL((ring_kernel<RING_ANALYSIS, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
             break;
         case RING_SYNTH:
-            hipLaunchKernelGGL((ring_kernel<RING_SYNTH, R, P>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
+            hipLaunchKernelGGL((ring_kernel<RING_SYNTH, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
             break;
         default:
-            hipLaunchKernelGGL((ring_kernel<RING_ITERATE, R, P>), grid, block, lds, s, A, map_in, map_out, K, b, ph);
+            hipLaunchKernelGGL((ring_kernel<RING_ITERATE, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
             break;
     }
 }
