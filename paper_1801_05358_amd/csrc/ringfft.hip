@@ -221,6 +221,20 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
     const bool anal = (MODE == RING_ANALYSIS || MODE == RING_ITERATE);
     const CR* chirp = L.bluestein ? A.chirp + L.chirp_off : nullptr;
     const CR zero = mk<R>(0, 0);
+    // e^{i m phi0} of the analysis unfold, computed once for the three
+    // fields (m = tid + nt r, the first kRot of them in registers), and the
+    // factor e^{i n phi0} between aliased m of the synthesis fold (-1 on
+    // HEALPix rings, whose phi0 = pi / n, 1 for phi0 = 0)
+    constexpr int kRot = 8;
+    CR rotu[kRot];
+    if (anal) {
+#pragma unroll
+        for (int r = 0; r < kRot; ++r) {
+            const int m = tid + nt * r;
+            rotu[r] = m <= mmax ? conjc(phase_rot<R>(m, P_.phi0_den)) : mk<R>(1, 0);
+        }
+    }
+    const CR alias_step = phase_rot<R>(n, P_.phi0_den);
 
     for (int f = 0; f < 3; ++f) {
         CP* ph = phase + (((int64_t)rhs * 3 + f) * A.npairs + p) * (mmax + 1) * 2;
@@ -233,15 +247,16 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                 if (j < n) {
                     CR cn = zero, cs = zero;
                     const int mstart = j - n * ((j + mmax) / n);
+                    CR rot = phase_rot<R>(mstart, P_.phi0_den);
                     for (int m = mstart; m <= mmax; m += n) {
                         const int a = m < 0 ? -m : m;
                         const CP fnd = ph[2 * a], fsd = ph[2 * a + 1];
                         CR fn = mk<R>((R)fnd.x, (R)fnd.y), fs = mk<R>((R)fsd.x, (R)fsd.y);
                         if (m < 0) { fn.y = -fn.y; fs.y = -fs.y; }
-                        const CR rot = phase_rot<R>(m, P_.phi0_den);
                         const CR tn = cmul(fn, rot), ts = cmul(fs, rot);
                         cn.x += tn.x; cn.y += tn.y;
                         cs.x += ts.x; cs.y += ts.y;
+                        rot = cmul(rot, alias_step);
                     }
                     // z = C_N + i C_S ; store conj(z)
                     v = mk<R>(cn.x - cs.y, -(cn.y + cs.x));
@@ -297,21 +312,26 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
         }
         if (anal) {
             dft_core<R>(buf, L, A);
-            for (int m = tid; m <= mmax; m += nt) {
+            // unfold: X_N = (Z_k + conj Z_{-k}) / 2,  X_S = (Z_k - conj Z_{-k}) / (2i)
+            auto unfold = [&](int m, CR rot) {
                 const int k = m % n;
                 const int k2 = (n - k) % n;
                 const int q1 = L.bluestein ? (int)brev(k, logM) : k;
                 const int q2 = L.bluestein ? (int)brev(k2, logM) : k2;
                 CR z1 = buf[pidx(q1)], z2 = buf[pidx(q2)];
                 if (L.bluestein) { z1 = cmul(z1, chirp[k]); z2 = cmul(z2, chirp[k2]); }
-                // X_N = (Z_k + conj Z_{-k}) / 2,  X_S = (Z_k - conj Z_{-k}) / (2i)
                 const CR xn = mk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
                 const CR xs = mk<R>(R(0.5) * (z1.y + z2.y), R(-0.5) * (z1.x - z2.x));
-                const CR rot = conjc(phase_rot<R>(m, P_.phi0_den));
                 const CR on = cmul(xn, rot), os = cmul(xs, rot);
                 ph[2 * m] = mk<P>((P)on.x, (P)on.y);
                 ph[2 * m + 1] = P_.has_s ? mk<P>((P)os.x, (P)os.y) : mk<P>(0, 0);
+            };
+#pragma unroll
+            for (int r = 0; r < kRot; ++r) {
+                const int m = tid + nt * r;
+                if (m <= mmax) unfold(m, rotu[r]);
             }
+            for (int m = tid + nt * kRot; m <= mmax; m += nt) unfold(m, conjc(phase_rot<R>(m, P_.phi0_den)));
             __syncthreads();
         }
     }
