@@ -112,32 +112,34 @@ void collect_events(dm_plan* p) {
 // --------------------------------------------------------------------------
 // transform building blocks
 // --------------------------------------------------------------------------
-// ring Fourier data of the plan's current precision: FP32 storage for the
-// mixed transforms (their products round the data to FP32 anyway), FP64
-// otherwise (also for a mixed plan's FP64 epilogue)
-void* phase_of(dm_plan* p) {
-    return (p->precision == DM_MIXED && p->d_phase32) ? (void*)p->d_phase32 : (void*)p->d_phase;
-}
+bool use_mfma(dm_plan* p, int nrhs);
+
+// ring Fourier data: FP32 storage for the mixed matrix-core transforms
+// (their products round the data to FP32 anyway), FP64 otherwise (the
+// vector kernels, FP64 plans, a mixed plan's FP64 epilogue)
+bool phase32(dm_plan* p, int nrhs) { return p->precision == DM_MIXED && p->d_phase32 && use_mfma(p, nrhs); }
+void* phase_of(dm_plan* p, int nrhs) { return phase32(p, nrhs) ? (void*)p->d_phase32 : (void*)p->d_phase; }
 
 void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const double* b, hipStream_t s) {
     Timed t(p, KC_RING, s);
-    HIPCHK(launch_ring(p, mode, nrhs, in, out, p->d_K, b, phase_of(p), s));
+    HIPCHK(launch_ring(p, mode, nrhs, in, out, p->d_K, b, phase_of(p, nrhs), phase32(p, nrhs), s));
     t.done();
 }
 
 // analysis + combine: alm = filter(A t) in (T, E, B); spin (nullable)
 // receives the same coefficients in the spin basis for the synthesis
-// batched matrix-core Legendre kernels: always for DM_MIXED, for DM_FP64
-// from 8 right-hand sides on (DMWF_MFMA=0/1 forces it off/on)
+// batched matrix-core Legendre kernels: for DM_MIXED from 2 right-hand
+// sides on (a single RHS fills 2 of the 16 product columns, and the FP64
+// vector kernels are faster: 70 against 51 iterations/s at Nside 1024,
+// lmax 2048), for DM_FP64 from 8 on; DMWF_MFMA=0/1 forces it off/on
 bool use_mfma(dm_plan* p, int nrhs) {
-    if (p->precision == DM_MIXED) return true;
     if (p->mfma_mode >= 0) return p->mfma_mode == 1;
-    return nrhs >= 8;
+    return nrhs >= (p->precision == DM_MIXED ? 2 : 8);
 }
 
 void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, double* alm, double* spin,
                   hipStream_t s, double* cpart = nullptr) {
-    const void* phase = phase_of(p);
+    const void* phase = phase_of(p, nrhs);
     const double* w = weighted ? p->d_pair_w : p->d_pair_one;
     int nslots = p->ana_chunks;
     {
@@ -158,7 +160,7 @@ void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, dou
 
 // synthesis from spin-basis coefficients
 void leg_synthesis(dm_plan* p, int nrhs, const double* spin, hipStream_t s) {
-    void* phase = phase_of(p);
+    void* phase = phase_of(p, nrhs);
     Timed t(p, KC_LEG_SYNTHESIS, s);
     if (use_mfma(p, nrhs)) {
         p->mfma_nct = 1;

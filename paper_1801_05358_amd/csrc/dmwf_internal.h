@@ -199,9 +199,9 @@ enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3 };
 // RING_ANALYSIS: map -> phase.  RING_SYNTH: phase -> map.
 // RING_ITERATE: phase -> (K x + b) -> phase.
 // RING_ITERATE with map_out != null also stores the updated messenger t.
-// phase: FP32 ring data for DM_MIXED plans, FP64 otherwise
+// phase: FP32 ring data if phase32, else FP64
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out,
-                       const double* K, const double* b, void* phase, hipStream_t s);
+                       const double* K, const double* b, void* phase, bool phase32, hipStream_t s);
 hipError_t ring_set_lds_limit(size_t bytes);
 
 // pointwise.hip

@@ -391,11 +391,11 @@ hipError_t set_lds_t(size_t bytes) {
 
 }  // namespace
 
-// FP32 transforms for mixed plans that carry the FP32 tables (opt-in at
-// plan creation), FP64 otherwise
+// FP64 transforms on FP64 ring data; on FP32 ring data (mixed plans) FP32
+// transforms if the plan carries the FP32 tables (opt-in), else FP64
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
-                       const double* b, void* phase, hipStream_t s) {
-    if (p->precision != DM_MIXED) {
+                       const double* b, void* phase, bool phase32, hipStream_t s) {
+    if (!phase32) {
         const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw);
         launch_ring_t<double, double>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
     } else if (p->d_tw32) {
