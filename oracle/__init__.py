@@ -12,7 +12,9 @@ What it follows (Kodi Ramanah, Lavaux & Wandelt 2018, arXiv:1801.05358):
 * the messenger chi^2 and its reduced two-equation form (Sec. 2, eqs 4, 8, 9);
 * the cooling of xi and the Heaviside truncation of the signal covariance
   (Sec. 2, text after eq 9);
-* the per-ell 3x3 signal covariance and per-pixel noise (Sec. 2.1, eqs 10-11);
+* the per-ell 3x3 signal covariance and per-pixel noise, diagonal or the
+  full correlated 3x3 block (Sec. 2.1, eqs 10-11);
+* distinct temperature and polarization masks (Appendix B);
 * Algorithm 1 (the polarized dual messenger loop);
 * constrained realizations (Sec. 2.2, eq 19);
 * the residual ||A x - y|| / ||y|| with A = 1 + S^1/2 N^-1 S^1/2 (Appendix C)

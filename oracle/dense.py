@@ -21,6 +21,20 @@ from .sht import lm_arrays, nalm
 from .dm import setup, messenger_filter
 
 
+def pixel_matrix(M):
+    """Dense [3 npix, 3 npix] of a per-pixel operator (diagonal [3, npix]
+    or 3x3 blocks [3, 3, npix]) in the map ordering (component-major)."""
+    if M.ndim == 2:
+        return np.diag(M.reshape(-1))
+    npix = M.shape[-1]
+    D = np.zeros((3 * npix, 3 * npix))
+    p = np.arange(npix)
+    for f in range(3):
+        for g in range(3):
+            D[f * npix + p, g * npix + p] = M[f, g]
+    return D
+
+
 def coords(lmax):
     """List of (field, l, m, part) for every real coordinate; part 0 = Re,
     1 = Im.  E and B start at l = 2."""
@@ -123,9 +137,9 @@ def wiener_filter(sht, d, ncov, obs, cl, Y=None):
     lmax = sht.lmax
     Y = synthesis_matrix(sht) if Y is None else Y
     st = setup(sht.grid, ncov, obs, d)
-    ninv = st["ninv"].reshape(-1)
+    NI = pixel_matrix(st["ninv"])
     S = prior_matrix(cl, lmax)
-    YtN = Y.T * ninv[None, :]
+    YtN = Y.T @ NI
     lhs = np.eye(S.shape[0]) + S @ (YtN @ Y)
     rhs = S @ (YtN @ st["d0"].reshape(-1))
     return x_to_alm(np.linalg.solve(lhs, rhs), lmax)
@@ -140,11 +154,10 @@ def messenger_fixed_point(sht, d, ncov, obs, cl, Y=None):
     w = np.tile(pixel_weights(sht.grid), 3)
     A = Y.T * w[None, :]
     F = filter_matrix(messenger_filter(cl, 0.0, st["tau"]), lmax)
-    Tp = np.tile(st["tau"] / pixel_weights(sht.grid), 3)
-    TN = Tp * st["ninv"].reshape(-1)
+    TN = pixel_matrix(st["tn"])
     FA = F @ A
-    lhs = np.eye(F.shape[0]) - FA @ Y + FA @ (TN[:, None] * Y)
-    rhs = FA @ (TN * st["d0"].reshape(-1))
+    lhs = np.eye(F.shape[0]) - FA @ Y + FA @ (TN @ Y)
+    rhs = FA @ (TN @ st["d0"].reshape(-1))
     return x_to_alm(np.linalg.solve(lhs, rhs), lmax)
 
 
@@ -154,7 +167,6 @@ def posterior_covariance(sht, ncov, obs, cl, Y=None):
     lmax = sht.lmax
     Y = synthesis_matrix(sht) if Y is None else Y
     st = setup(sht.grid, ncov, obs, np.zeros((3, sht.grid["npix"])))
-    ninv = st["ninv"].reshape(-1)
     S = prior_matrix(cl, lmax)
-    lhs = np.eye(S.shape[0]) + S @ ((Y.T * ninv[None, :]) @ Y)
+    lhs = np.eye(S.shape[0]) + S @ ((Y.T @ pixel_matrix(st["ninv"])) @ Y)
     return np.linalg.solve(lhs, S)

@@ -4,7 +4,9 @@
 Follows the paper step by step (Kodi Ramanah, Lavaux & Wandelt 2018):
 
 * eq 4 / Algorithm 1: the messenger covariance T = alpha 1 with alpha the
-  smallest noise eigenvalue.  On a grid with quadrature weights w_p the
+  smallest noise eigenvalue; the pixel noise is diagonal or the full 3x3
+  block of eq 11, with a common mask or distinct T and P masks
+  (Appendix B).  On a grid with quadrature weights w_p the
   harmonic-space messenger variance is tau = min_p (alpha_p w_p) and the
   pixel-space one T_p = tau / w_p (for HEALPix, w = 4 pi / N_pix and
   tau = alpha w is the sphere's counterpart of sigma^-1 alpha);
@@ -39,20 +41,80 @@ from .sht import alm_dot, lm_arrays
 # ----------------------------------------------------------------------------
 # setup (eq 4, Algorithm 1 initialisation)
 # ----------------------------------------------------------------------------
+def observed(obs, npix):
+    """Per-component observation indicator [3, npix] bool.  obs: None (all
+    observed), a common mask [npix], a pair (obs_t, obs_p) of a temperature
+    and a polarization mask (Q and U share obs_p), or [3, npix]."""
+    if obs is None:
+        return np.ones((3, npix), dtype=bool)
+    if isinstance(obs, (tuple, list)):
+        ot, op = (np.asarray(x, dtype=bool).reshape(npix) for x in obs)
+        return np.stack([ot, op, op])
+    o = np.asarray(obs, dtype=bool)
+    return np.broadcast_to(o.reshape(-1, npix), (3, npix)).copy()
+
+
+SYM6 = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def noise_blocks(ncov6):
+    """[6, npix] in the order (II, IQ, IU, QQ, QU, UU) -> N [npix, 3, 3]."""
+    N = np.zeros((ncov6.shape[1], 3, 3))
+    for k, (i, j) in enumerate(SYM6):
+        N[:, i, j] = ncov6[k]
+        N[:, j, i] = ncov6[k]
+    return N
+
+
+def pix_apply(M, x):
+    """Per-pixel operator on maps [..., 3, npix]: M is diagonal [3, npix]
+    or a 3x3 block per pixel [3, 3, npix]."""
+    if M.ndim == 2:
+        return M * x
+    return np.einsum("fgp,...gp->...fp", M, x)
+
+
 def setup(grid, ncov, obs, d):
-    """ncov [3, npix] per-pixel (II, QQ, UU) variances, obs [npix] bool,
-    d [..., 3, npix].  Returns dict(tau, K [3, npix], b [..., 3, npix],
-    ninv [3, npix], d0 = d with the mask zeroed)."""
+    """ncov: per-pixel noise covariance, diagonal [3, npix] (II, QQ, UU) or
+    the symmetric 3x3 block of eq 11 [6, npix] (II, IQ, IU, QQ, QU, UU);
+    obs: see observed(); d [..., 3, npix].
+
+    Masks follow Appendix B: with N_p = Sigma C Sigma and Sigma^-1 = 0 on
+    the unobserved components, the inverse noise covariance P_p is the
+    block of N_p^-1 on the observed components, zero elsewhere (for a
+    diagonal N_p simply 1 / N_pf on observed components).  The messenger
+    variance uses alpha_p = 1 / lambda_max(P_p): the smallest eigenvalue of
+    N_p when all components are observed, and its limit as the unobserved
+    variances go to infinity at fixed correlations otherwise.  Appendix B's
+    messenger equation t = (N_bar^-1 + T^-1)^-1 (T^-1 u_x + N_bar^-1 d)
+    with N_bar = N - T reduces to t = K u_x + b, K = 1 - T_p P_p,
+    b = T_p P_p d0.
+
+    Returns dict(tau, K, b, ninv = P, tn = T_p P, d0 = d zeroed on
+    unobserved components, obs = [3, npix] indicator); K, ninv and tn are
+    [3, npix] for diagonal noise and [3, 3, npix] otherwise."""
+    npix = grid["npix"]
     w = pixel_weights(grid)
-    obs = np.ones(grid["npix"], dtype=bool) if obs is None else np.asarray(obs, dtype=bool)
-    alpha_p = np.min(ncov, axis=0)                 # smallest eigenvalue of N_p
-    tau = float(np.min(alpha_p[obs] * w[obs]))
-    ninv = np.where(obs[None, :], 1.0 / np.where(obs[None, :], ncov, 1.0), 0.0)
+    o = observed(obs, npix)
+    seen = o.any(axis=0)
+    if ncov.shape[0] == 3:
+        ninv = np.where(o, 1.0 / np.where(o, ncov, 1.0), 0.0)
+        alpha_p = np.min(np.where(o, ncov, np.inf), axis=0)   # smallest eigenvalue of N_p
+    else:
+        N = noise_blocks(ncov)
+        P = np.zeros_like(N)
+        P[seen] = np.linalg.inv(N[seen])
+        P *= o.T[:, :, None] & o.T[:, None, :]
+        alpha_p = np.full(npix, np.inf)
+        alpha_p[seen] = 1.0 / np.linalg.eigvalsh(P[seen])[:, -1]
+        ninv = np.moveaxis(P, 0, -1)
+    tau = float(np.min(alpha_p[seen] * w[seen]))
     Tp = tau / w
-    K = 1.0 - Tp[None, :] * ninv
-    d0 = np.where(obs, d, 0.0)
-    b = Tp * ninv * d0
-    return dict(tau=tau, K=K, b=b, ninv=ninv, d0=d0, obs=obs)
+    tn = Tp * ninv
+    K = (1.0 - tn) if ninv.ndim == 2 else (np.eye(3)[:, :, None] - tn)
+    d0 = np.where(o, d, 0.0)
+    b = pix_apply(tn, d0)
+    return dict(tau=tau, K=K, b=b, ninv=ninv, tn=tn, d0=d0, obs=o)
 
 
 # ----------------------------------------------------------------------------
@@ -121,7 +183,7 @@ def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False):
             t_hat = sht.analysis(t)
             u = apply_blocks(F, t_hat, lmax)
             ux = sht.synthesis(u)
-            t = K * ux + b
+            t = pix_apply(K, ux) + b
             if u_prev is not None:
                 cauchy.append(cauchy_ratio(u, u_prev, lmax))
             u_prev = u
@@ -173,7 +235,7 @@ def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max
             t_hat = sht.analysis(t)
             u = apply_blocks(F, t_hat, lmax)
             ux = sht.synthesis(u)
-            t = K * ux + b
+            t = pix_apply(K, ux) + b
             c = cauchy_ratio(u, u_prev, lmax)
             trace.append(c)
             steps.append(j)
@@ -198,8 +260,8 @@ def residual(sht, u, d, ncov, obs, cl, ux=None):
         ux = sht.synthesis(u)
     half = matrix_function(cl, lambda s: np.sqrt(np.maximum(s, 0.0)))
     ihalf = matrix_function(cl, lambda s: np.where(s > 0, 1.0 / np.sqrt(np.where(s > 0, s, 1.0)), 0.0))
-    r = apply_blocks(ihalf, u, lmax) + apply_blocks(half, sht.adjoint(ninv * (ux - d0)), lmax)
-    y = apply_blocks(half, sht.adjoint(ninv * d0), lmax)
+    r = apply_blocks(ihalf, u, lmax) + apply_blocks(half, sht.adjoint(pix_apply(ninv, ux - d0)), lmax)
+    y = apply_blocks(half, sht.adjoint(pix_apply(ninv, d0)), lmax)
     nr = sum(alm_dot(r[f], r[f], lmax) for f in range(3))
     ny = sum(alm_dot(y[f], y[f], lmax) for f in range(3))
     return float(np.sqrt(nr / ny))
@@ -214,7 +276,7 @@ def chi2(sht, u, d, ncov, obs, cl, ux=None):
     res = st["d0"] - ux
     sinv = matrix_function(cl, lambda s: np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0))
     su = apply_blocks(sinv, u, lmax)
-    return float(np.sum(res * res * st["ninv"]) + sum(alm_dot(u[f], su[f], lmax) for f in range(3)))
+    return float(np.sum(res * pix_apply(st["ninv"], res)) + sum(alm_dot(u[f], su[f], lmax) for f in range(3)))
 
 
 def cauchy_ratio(u, u_prev, lmax):

@@ -21,12 +21,22 @@ Recipes (all random numbers from NumPy's PCG64 with explicit seeds
   (b) scan-like  sigma0^2 * R^(1 - h),  h = (1 + cos gamma) / 2, gamma the
       angle to a tilted scan pole at (theta, phi) = (60 deg, 45 deg); the
       range is exactly R : 1;
-* noise realizations n_p = sqrt(N_p) g on observed pixels.
+* noise realizations n_p = sqrt(N_p) g on observed pixels;
+* correlated pixel noise (3x3 per pixel): off-diagonal terms as fixed
+  fractions of the geometric means of the variances (correlation matrix
+  [[1, .3, -.15], [.3, 1, .2], [-.15, .2, 1]]), and distinct temperature
+  and polarization masks (the polarization band 3 deg narrower, the two
+  with independent holes, at least 1.5 pixel sides in radius, and the
+  temperature mask with twice as many, so
+  that some pixels observe T only and some Q, U only); realizations
+  L_p g with L_p the Cholesky factor of N_p, zero on unobserved
+  components.
 """
 
 import numpy as np
 
-ROLE_SIGNAL, ROLE_NOISE, ROLE_HOLES, ROLE_PATTERN, ROLE_CR_SIGNAL, ROLE_CR_NOISE = range(6)
+(ROLE_SIGNAL, ROLE_NOISE, ROLE_HOLES, ROLE_PATTERN, ROLE_CR_SIGNAL, ROLE_CR_NOISE, ROLE_HOLES_P,
+ ROLE_NOISE6) = range(8)
 
 
 def seed_for(cfg, role, k=0):
@@ -164,6 +174,33 @@ def draw_noise(ncov, obs, rng):
     return np.where(obs[None, :], n, 0.0)
 
 
+# correlated pixel noise: the layout (II, IQ, IU, QQ, QU, UU) of a symmetric
+# 3x3 per-pixel covariance
+SYM6 = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def correlate_noise(ncov, rho_tp=0.3, rho_qu=0.2):
+    """A correlated per-pixel covariance built from diagonal variances
+    (II, QQ, UU): N_IQ = rho_tp sqrt(II QQ), N_IU = -rho_tp/2 sqrt(II UU),
+    N_QU = rho_qu sqrt(QQ UU) (positive definite for these small rho).
+    Returns [6, npix] in the SYM6 layout."""
+    II, QQ, UU = ncov
+    return np.stack([II, rho_tp * np.sqrt(II * QQ), -0.5 * rho_tp * np.sqrt(II * UU), QQ,
+                     rho_qu * np.sqrt(QQ * UU), UU])
+
+
+def draw_noise6(ncov6, obs3, rng):
+    """n_p = L_p g with L_p L_p^T = N_p (per pixel), zero on unobserved
+    components.  obs3: [3, npix] bool."""
+    N = np.zeros((ncov6.shape[1], 3, 3))
+    for k, (i, j) in enumerate(SYM6):
+        N[:, i, j] = ncov6[k]
+        N[:, j, i] = ncov6[k]
+    L = np.linalg.cholesky(N)
+    n = np.einsum("pij,jp->ip", L, rng.standard_normal((3, ncov6.shape[1])))
+    return np.where(obs3, n, 0.0)
+
+
 # ----------------------------------------------------------------------------
 # workload configurations
 # ----------------------------------------------------------------------------
@@ -210,3 +247,23 @@ def signal_alm(cfg, lmax, k=0, role=ROLE_SIGNAL):
 
 def noise_map(cfg, ncov, obs, k=0, role=ROLE_NOISE):
     return draw_noise(ncov, obs, rng_for(cfg, role, k))
+
+
+def correlated_problem(cfg, **kw):
+    """make_problem plus correlated noise and distinct T / P masks: adds
+    ncov6 [6, npix] (SYM6 layout), obs_t and obs_p [npix] bool and obs3
+    [3, npix] (I observed where obs_t, Q and U where obs_p)."""
+    p = make_problem(cfg, **kw)
+    th, ph = p["theta"], p["phi"]
+    holes = max(2 * p["holes"], 4)
+    # holes at least 1.5 pixel sides across, so that they remove pixels on
+    # coarse grids too
+    rad = max(HOLE_RADIUS_DEG, 1.5 * float(np.rad2deg(np.sqrt(4 * np.pi / th.size))))
+    obs_t = band_mask(th, p["band"]) & hole_mask(th, ph, holes, rad, rng_for(cfg, ROLE_HOLES))
+    obs_p = band_mask(th, p["band"] - 3.0) & hole_mask(th, ph, holes // 2, rad, rng_for(cfg, ROLE_HOLES_P))
+    p.update(ncov6=correlate_noise(p["ncov"]), obs_t=obs_t, obs_p=obs_p, obs3=np.stack([obs_t, obs_p, obs_p]))
+    return p
+
+
+def noise_map6(cfg, ncov6, obs3, k=0, role=ROLE_NOISE6):
+    return draw_noise6(ncov6, obs3, rng_for(cfg, role, k))
