@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 2
+#define DMWF_ABI_VERSION 3
 
 typedef enum {
     DM_OK = 0,
@@ -70,9 +70,11 @@ typedef enum { DM_GRID_HEALPIX_RING = 0, DM_GRID_GAUSS_LEGENDRE = 1 } dm_grid_ki
  *           double precision.  I/O buffers are always double.            */
 typedef enum { DM_FP64 = 0, DM_MIXED = 1 } dm_precision;
 
-/* Per-pixel noise covariance layout.  DM_NCOV_DIAG3: [3][npix] variances
- * (II, QQ, UU), i.e. N_p diagonal (eq 11 with vanishing cross terms).    */
-typedef enum { DM_NCOV_DIAG3 = 0 } dm_ncov;
+/* Per-pixel noise covariance layout (eq 11).
+ * DM_NCOV_DIAG3: [3][npix] variances (II, QQ, UU), N_p diagonal.
+ * DM_NCOV_SYM6:  [6][npix] the symmetric 3x3 block of eq 11 in the order
+ *                (II, IQ, IU, QQ, QU, UU): correlated noise.              */
+typedef enum { DM_NCOV_DIAG3 = 0, DM_NCOV_SYM6 = 1 } dm_ncov;
 
 typedef struct {
     int kind;      /* dm_grid_kind                                        */
@@ -146,12 +148,35 @@ dm_status dm_plan_info(const dm_plan* plan, int64_t* npix, int64_t* nalm, int* n
  * finite; E and B entries below l = 2 are ignored.                        */
 dm_status dm_set_spectra(dm_plan* plan, const double* cl);
 
-/* Noise covariance (eq 11, diagonal) and mask: ncov [3][npix] variances,
- * obs [npix] with 1 = observed, 0 = masked (NULL = all observed).
- * Observed variances must be finite and > 0; masked pixels get N^-1 = 0
- * (Appendix B).  Sets tau = min over observed pixels of (min variance x
- * pixel weight), the messenger covariance of eq 4.                       */
+/* Noise covariance (eq 11) with one mask common to I, Q and U:
+ * dm_set_noise_masks(plan, ncov, layout, obs, obs).                       */
 dm_status dm_set_noise(dm_plan* plan, const double* ncov, dm_ncov layout, const uint8_t* obs);
+
+/* Noise covariance (eq 11) with distinct temperature and polarization masks
+ * (Appendix B).  ncov: host [3][npix] (DM_NCOV_DIAG3) or [6][npix]
+ * (DM_NCOV_SYM6), copied.  obs_t: host [npix], nonzero = I observed;
+ * obs_p: host [npix], nonzero = Q and U observed; NULL = all observed.
+ *
+ * The inverse noise covariance P_p is the block of N_p^-1 on the observed
+ * components with zero rows and columns elsewhere: Appendix B's
+ * N = Sigma C Sigma with Sigma^-1 = 0 on unobserved components (for
+ * diagonal noise, 1 / variance on observed components).  The messenger
+ * covariance of eq 4 is T_p = tau / w_p with w_p the pixel weight and
+ * tau = min over pixels with an observed component of w_p / lambda_max(P_p)
+ * (the smallest eigenvalue of N_p times w_p when all is observed); the
+ * update of eq 9 is t = (1 - T_p P_p) u_x + T_p P_p d.
+ *
+ * Requirements (else DM_EINVAL, nothing changed): DM_NCOV_DIAG3 - every
+ * observed component's variance finite and > 0; DM_NCOV_SYM6 - on every
+ * pixel with an observed component all six entries finite and N_p
+ * positive definite (its unobserved components enter through the
+ * correlation matrix C); at least one observed component.  Entries of
+ * pixels with nothing observed are ignored.  Another layout value is
+ * DM_EUNSUPPORTED.  With DM_NCOV_SYM6 each iteration runs the pixel
+ * update as its own pass over the maps (the three fields of a pixel are
+ * coupled), so it costs a little more than diagonal noise.                */
+dm_status dm_set_noise_masks(dm_plan* plan, const double* ncov, dm_ncov layout, const uint8_t* obs_t,
+                             const uint8_t* obs_p);
 
 /* Cooling schedule; the default is the fixed mode {1e3, 20, 10}.          */
 dm_status dm_set_schedule(dm_plan* plan, const dm_schedule* schedule);
@@ -211,7 +236,7 @@ dm_status dm_iterate(dm_plan* plan, int nrhs, const double* d, const double* t_i
  * when enabled: enable != 0 turns recording on and clears the totals.
  * dm_kernel_times writes, for kernel class k < *count (0 Legendre
  * analysis, 1 Legendre synthesis, 2 ring FFT + pointwise, 3 combine and
- * filter), the total milliseconds to ms[k] and the number of launches to
+ * filter, 4 the separate 3x3 pixel update), the total milliseconds to ms[k] and the number of launches to
  * launches[k].                                                            */
 dm_status dm_profile_enable(dm_plan* plan, int enable);
 dm_status dm_kernel_times(dm_plan* plan, double* ms, int64_t* launches, int* count);

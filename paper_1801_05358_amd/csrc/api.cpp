@@ -126,6 +126,25 @@ void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const d
     t.done();
 }
 
+// the pixel step of one iteration (eq 9): ring Fourier data of u_x -> the
+// messenger t = K u_x + b -> ring Fourier data of t; t_out (nullable)
+// receives t.  Diagonal noise runs it in one ring pass per field; 3x3 noise
+// couples the three fields of a pixel, which one ring pass holds one at a
+// time, so there it is synthesis, the 3x3 update and analysis in turn.
+void messenger_step(dm_plan* p, int nrhs, double* t_out, hipStream_t s) {
+    if (p->ncov_layout != DM_NCOV_SYM6) {
+        ring(p, RING_ITERATE, nrhs, nullptr, t_out, p->d_b, s);
+        return;
+    }
+    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+    {
+        Timed t(p, KC_PIXEL, s);
+        HIPCHK(launch_update6(p, nrhs, p->d_ux, p->d_b, t_out, s));
+        t.done();
+    }
+    ring(p, RING_ANALYSIS, nrhs, p->d_ux, nullptr, nullptr, s);
+}
+
 // analysis + combine: alm = filter(A t) in (T, E, B); spin (nullable)
 // receives the same coefficients in the spin basis for the synthesis
 // batched matrix-core Legendre kernels: for DM_MIXED from 2 right-hand
@@ -285,7 +304,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 leg_synthesis(p, nrhs, p->d_alm_spin, s);
                 if (!last) {
                     // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
-                    ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, s);
+                    messenger_step(p, nrhs, nullptr, s);
                 } else {
                     ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
                 }
@@ -333,7 +352,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                     done = true;
                     break;
                 }
-                ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_b, s);
+                messenger_step(p, nrhs, nullptr, s);
                 if (conv) break;
             }
         }
@@ -400,6 +419,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
     dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
+    dfree(p->d_ninv6); dfree(p->d_tn6);
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
     dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
@@ -690,35 +710,59 @@ dm_status dm_set_spectra(dm_plan* p, const double* cl) {
 }
 
 dm_status dm_set_noise(dm_plan* p, const double* ncov, dm_ncov layout, const uint8_t* obs) {
+    return dm_set_noise_masks(p, ncov, layout, obs, obs);
+}
+
+dm_status dm_set_noise_masks(dm_plan* p, const double* ncov, dm_ncov layout, const uint8_t* obs_t,
+                             const uint8_t* obs_p) {
     return guarded(p, [&] {
         REQUIRE(ncov != nullptr, DM_EINVAL, "ncov is null");
-        REQUIRE(layout == DM_NCOV_DIAG3, DM_EUNSUPPORTED, "only DM_NCOV_DIAG3 noise is implemented");
+        REQUIRE(layout == DM_NCOV_DIAG3 || layout == DM_NCOV_SYM6, DM_EUNSUPPORTED, "unknown noise layout");
         const int64_t n = p->npix;
+        const int rows = layout == DM_NCOV_SYM6 ? 6 : 3;
+        // observation bits: 1 = I, 2 = Q and U
+        std::vector<uint8_t> bits(n);
         int64_t nobs = 0;
         for (int64_t q = 0; q < n; ++q) {
-            if (obs && !obs[q]) continue;
+            const int m = ((!obs_t || obs_t[q]) ? 1 : 0) | ((!obs_p || obs_p[q]) ? 2 : 0);
+            bits[q] = (uint8_t)m;
+            if (!m) continue;
             ++nobs;
-            for (int f = 0; f < 3; ++f) {
-                const double v = ncov[f * n + q];
-                REQUIRE(std::isfinite(v) && v > 0, DM_EINVAL,
-                        "observed noise variances must be finite and > 0 (pixel " + std::to_string(q) + ")");
+            if (layout == DM_NCOV_DIAG3) {
+                for (int f = 0; f < 3; ++f) {
+                    if (!(m & (f == 0 ? 1 : 2))) continue;
+                    const double v = ncov[f * n + q];
+                    REQUIRE(std::isfinite(v) && v > 0, DM_EINVAL,
+                            "observed noise variances must be finite and > 0 (pixel " + std::to_string(q) + ")");
+                }
+            } else {
+                double e[6];
+                for (int k = 0; k < 6; ++k) e[k] = ncov[k * n + q];
+                bool ok = true;
+                for (int k = 0; k < 6; ++k) ok = ok && std::isfinite(e[k]);
+                // Sylvester: leading minors of [[II IQ IU] [IQ QQ QU] [IU QU UU]] > 0
+                const double m1 = e[0], m2 = e[0] * e[3] - e[1] * e[1];
+                const double m3 = e[0] * (e[3] * e[5] - e[4] * e[4]) - e[1] * (e[1] * e[5] - e[4] * e[2]) +
+                                  e[2] * (e[1] * e[4] - e[3] * e[2]);
+                REQUIRE(ok && m1 > 0 && m2 > 0 && m3 > 0, DM_EINVAL,
+                        "the 3x3 noise covariance must be finite and positive definite on pixels with an "
+                        "observed component (pixel " + std::to_string(q) + ")");
             }
         }
         REQUIRE(nobs > 0, DM_EINVAL, "every pixel is masked");
         p->noise_set = false;
-        double* d_ncov = nullptr;
-        HIPCHK(hipMalloc((void**)&d_ncov, 3 * n * sizeof(double)));
-        std::unique_ptr<double, void (*)(double*)> guard(d_ncov, [](double* x) { (void)hipFree(x); });
-        upload(p, d_ncov, ncov, 3 * n);
-        uint8_t* dobs = nullptr;
-        if (obs) {
-            upload(p, p->d_obs, obs, n);
-            dobs = p->d_obs;
-        } else {
-            HIPCHK(hipMemsetAsync(p->d_obs, 1, n, p->stream));
+        if (layout == DM_NCOV_SYM6 && !p->d_ninv6) {
+            dalloc(p, p->d_ninv6, 6 * (size_t)n);
+            dalloc(p, p->d_tn6, 6 * (size_t)n);
         }
+        p->ncov_layout = layout;
+        double* d_ncov = nullptr;
+        HIPCHK(hipMalloc((void**)&d_ncov, rows * n * sizeof(double)));
+        std::unique_ptr<double, void (*)(double*)> guard(d_ncov, [](double* x) { (void)hipFree(x); });
+        upload(p, d_ncov, ncov, rows * n);
+        upload(p, p->d_obs, bits.data(), n);
         double* ring_min = p->d_red + 64;
-        HIPCHK(launch_tau_parts(p, d_ncov, dobs, ring_min, p->stream));
+        HIPCHK(launch_tau_parts(p, d_ncov, ring_min, p->stream));
         std::vector<double> rm(p->nrings);
         HIPCHK(hipMemcpyAsync(rm.data(), ring_min, rm.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
         HIPCHK(hipStreamSynchronize(p->stream));
@@ -726,7 +770,7 @@ dm_status dm_set_noise(dm_plan* p, const double* ncov, dm_ncov layout, const uin
         for (double v : rm) tau = std::min(tau, v);
         REQUIRE(std::isfinite(tau) && tau > 0, DM_EINVAL, "no valid observed pixel");
         p->tau = tau;
-        HIPCHK(launch_noise_setup(p, d_ncov, dobs, tau, p->stream));
+        HIPCHK(launch_noise_setup(p, d_ncov, tau, p->stream));
         HIPCHK(hipStreamSynchronize(p->stream));
         p->noise_set = true;
     });
@@ -925,7 +969,7 @@ dm_status dm_iterate(dm_plan* p, int nrhs, const double* d, const double* t_in, 
         for (int i = 0; i < niter; ++i) {
             leg_analysis(p, nrhs, true, p->d_filters, p->d_alm, p->d_alm_spin, p->stream);
             leg_synthesis(p, nrhs, p->d_alm_spin, p->stream);
-            ring(p, RING_ITERATE, nrhs, nullptr, (i == niter - 1) ? dt : nullptr, p->d_b, p->stream);
+            messenger_step(p, nrhs, (i == niter - 1) ? dt : nullptr, p->stream);
         }
         HIPCHK(hipMemcpyAsync(alm, p->d_alm, na * sizeof(double), hipMemcpyDeviceToHost, p->stream));
         if (t_out) HIPCHK(hipMemcpyAsync(t_out, dt, nm * sizeof(double), hipMemcpyDeviceToHost, p->stream));

@@ -21,7 +21,7 @@ constexpr int kCoefStride = 6;   // A0, B0, alpha, alpha*beta, gamma, pad
 constexpr int kSeedFields = 6;
 
 // Kernel classes for the optional event timing.
-enum KernelClass { KC_LEG_ANALYSIS = 0, KC_LEG_SYNTHESIS = 1, KC_RING = 2, KC_COMBINE = 3, KC_COUNT = 4 };
+enum KernelClass { KC_LEG_ANALYSIS = 0, KC_LEG_SYNTHESIS = 1, KC_RING = 2, KC_COMBINE = 3, KC_PIXEL = 4, KC_COUNT = 5 };
 
 struct RingTables {
     // per ring
@@ -112,10 +112,13 @@ struct dm_plan {
     // noise
     bool noise_set = false;
     double tau = 0.0;
-    double* d_K = nullptr;             // [3][npix]  1 - T N^-1
-    double* d_tn = nullptr;            // [3][npix]  T N^-1
-    double* d_ninv = nullptr;          // [3][npix]  N^-1 (0 in the mask)
-    uint8_t* d_obs = nullptr;          // [npix]
+    int ncov_layout = DM_NCOV_DIAG3;   // of the last dm_set_noise
+    double* d_K = nullptr;             // [3][npix]  1 - T N^-1        (diagonal noise)
+    double* d_tn = nullptr;            // [3][npix]  T N^-1            (diagonal noise)
+    double* d_ninv = nullptr;          // [3][npix]  N^-1, 0 unobserved (diagonal noise)
+    double* d_ninv6 = nullptr;         // [6][npix]  P = N^-1 on observed components (3x3 noise)
+    double* d_tn6 = nullptr;           // [6][npix]  T P (3x3 noise)
+    uint8_t* d_obs = nullptr;          // [npix] bit 0: I observed, bit 1: Q and U observed
     double* d_ring_w = nullptr;        // [nrings] pixel weight per ring
     int64_t* d_ring_off = nullptr;     // [nrings]
     int* d_ring_n = nullptr;           // [nrings]
@@ -154,8 +157,8 @@ struct dm_plan {
 
     // timing
     bool profiling = false;
-    double kc_ms[dmwf::KC_COUNT] = {0, 0, 0, 0};
-    int64_t kc_n[dmwf::KC_COUNT] = {0, 0, 0, 0};
+    double kc_ms[dmwf::KC_COUNT] = {0, 0, 0, 0, 0};
+    int64_t kc_n[dmwf::KC_COUNT] = {0, 0, 0, 0, 0};
     dmwf::GpuEvents ev;
 };
 
@@ -205,13 +208,18 @@ hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, dou
 hipError_t ring_set_lds_limit(size_t bytes);
 
 // pointwise.hip
-// alpha_p w_p per observed pixel, min-reduced per ring -> ring_min [nrings]
-hipError_t launch_tau_parts(dm_plan* p, const double* ncov, const uint8_t* obs, double* ring_min, hipStream_t s);
-// K, T N^-1 and N^-1 from the noise, the mask and tau
-hipError_t launch_noise_setup(dm_plan* p, const double* ncov, const uint8_t* obs, double tau, hipStream_t s);
-// d0 = mask(d), b = T N^-1 d0
+// alpha_p w_p per pixel with an observed component, min-reduced per ring
+// -> ring_min [nrings]; with 3x3 noise also P_p -> d_ninv6.  The mask bits
+// are d_obs, the layout p->ncov_layout.
+hipError_t launch_tau_parts(dm_plan* p, const double* ncov, double* ring_min, hipStream_t s);
+// K, T N^-1 and N^-1 (diagonal) or T P (3x3) from the noise, the mask and tau
+hipError_t launch_noise_setup(dm_plan* p, const double* ncov, double tau, hipStream_t s);
+// d0 = d on observed components, b = T N^-1 d0
 hipError_t launch_data_setup(dm_plan* p, int nrhs, const double* d, double* d0, double* b, hipStream_t s);
-// in place: ux <- N^-1 (ux - d0), b <- N^-1 d0; chi_parts [nrhs][nrings] += (d0-ux)^2 N^-1
+// 3x3 noise, in place: ux <- ux - T P ux + b; t_out (nullable) gets a copy
+hipError_t launch_update6(dm_plan* p, int nrhs, double* ux, const double* b, double* t_out, hipStream_t s);
+// in place: ux <- N^-1 (ux - d0), b <- N^-1 d0;
+// chi_parts [nrhs][nrings] = sum (d0-ux)^T N^-1 (d0-ux)
 hipError_t launch_residual_maps(dm_plan* p, int nrhs, double* ux, const double* d0, double* b,
                                 double* chi_parts, hipStream_t s);
 // per (rhs, m, block) sums: |u-uprev|^2, |u|^2, |r|^2, |y|^2, u^T S^+ u

@@ -2,10 +2,22 @@
 // initialisation), per-pixel pieces of the diagnostics (eq 3 chi^2 and the
 // residual of Appendix C), and deterministic fixed-order reductions.
 //
-//   alpha_p = min_f N_p,f (smallest eigenvalue of a diagonal N_p),
-//   tau     = min over observed p of alpha_p w_p  (w_p pixel weight),
-//   T_p     = tau / w_p,   K = 1 - T_p N^-1,   T N^-1,  N^-1 = 0 if masked,
-//   d0      = d on observed pixels, 0 in the mask,   b = T N^-1 d0.
+// Observation is per component: bit 0 of obs[p] = I observed, bit 1 = Q
+// and U observed (distinct temperature and polarization masks, Appendix
+// B).  With P_p the inverse noise covariance on the observed components
+// (zero rows and columns elsewhere):
+//
+//   alpha_p = 1 / lambda_max(P_p)  (the smallest eigenvalue of N_p when
+//             every component is observed),
+//   tau     = min over pixels with an observed component of alpha_p w_p,
+//   T_p     = tau / w_p,   K = 1 - T_p P_p,   b = T_p P_p d0,
+//   d0      = d on observed components, 0 elsewhere.
+//
+// Diagonal noise (II, QQ, UU) keeps P, K and T P as [3][npix].  The
+// correlated 3x3 block of eq 11 keeps P and T P as symmetric 3x3 per pixel,
+// [6][npix] in the order (II, IQ, IU, QQ, QU, UU); there P_p is the block of
+// N_p^-1 on the observed components, i.e. Appendix B's N = Sigma C Sigma
+// with Sigma^-1 = 0 on the unobserved ones.
 #include "dmwf_internal.h"
 
 namespace dmwf {
@@ -40,6 +52,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+__device__ __forceinline__ int comp_bit(int f) { return f == 0 ? 1 : 2; }
+
 // one block per ring
 __global__ void tau_kernel(int64_t npix, const int64_t* __restrict__ roff, const int* __restrict__ rn,
                            const double* __restrict__ rw, const double* __restrict__ ncov,
@@ -52,8 +66,10 @@ __global__ void tau_kernel(int64_t npix, const int64_t* __restrict__ roff, const
     double v = INFINITY;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const int64_t q = o + j;
-        if (obs && !obs[q]) continue;
-        const double a = fmin(ncov[q], fmin(ncov[npix + q], ncov[2 * npix + q]));
+        const int m = obs[q];
+        double a = INFINITY;
+        if (m & 1) a = ncov[q];
+        if (m & 2) a = fmin(a, fmin(ncov[npix + q], ncov[2 * npix + q]));
         v = fmin(v, a * w);
     }
     v = block_min(v, sh);
@@ -71,7 +87,7 @@ __global__ void noise_kernel(int64_t npix, const int64_t* __restrict__ roff, con
     const double T = tau / rw[r];
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const int64_t q = (int64_t)f * npix + o + j;
-        const bool ok = !obs || obs[o + j];
+        const bool ok = (obs[o + j] & comp_bit(f)) != 0;
         const double ni = ok ? 1.0 / ncov[q] : 0.0;
         ninv[q] = ni;
         tn[q] = T * ni;
@@ -86,10 +102,186 @@ __global__ void data_kernel(int64_t npix, int64_t total, const double* __restric
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t q = i % (3 * npix);
         const int64_t pix = q % npix;
-        const double v = (!obs || obs[pix]) ? d[i] : 0.0;
+        const int f = (int)(q / npix);
+        const double v = (obs[pix] & comp_bit(f)) ? d[i] : 0.0;
         d0[i] = v;
         b[i] = tn[q] * v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// correlated 3x3 pixel noise
+// ---------------------------------------------------------------------------
+// symmetric [[a b c] [b d e] [c e f]]
+struct Sym3 {
+    double a, b, c, d, e, f;
+};
+
+__device__ __forceinline__ Sym3 load_sym(const double* __restrict__ m, int64_t npix, int64_t q) {
+    return Sym3{m[q], m[npix + q], m[2 * npix + q], m[3 * npix + q], m[4 * npix + q], m[5 * npix + q]};
+}
+
+__device__ __forceinline__ void store_sym(double* __restrict__ m, int64_t npix, int64_t q, const Sym3& s) {
+    m[q] = s.a;
+    m[npix + q] = s.b;
+    m[2 * npix + q] = s.c;
+    m[3 * npix + q] = s.d;
+    m[4 * npix + q] = s.e;
+    m[5 * npix + q] = s.f;
+}
+
+// inverse by cofactors (N symmetric positive definite, checked on the host)
+__device__ __forceinline__ Sym3 sym_inverse(const Sym3& n) {
+    const double c00 = n.d * n.f - n.e * n.e;
+    const double c01 = n.c * n.e - n.b * n.f;
+    const double c02 = n.b * n.e - n.c * n.d;
+    const double c11 = n.a * n.f - n.c * n.c;
+    const double c12 = n.b * n.c - n.a * n.e;
+    const double c22 = n.a * n.d - n.b * n.b;
+    const double id = 1.0 / (n.a * c00 + n.b * c01 + n.c * c02);
+    return Sym3{c00 * id, c01 * id, c02 * id, c11 * id, c12 * id, c22 * id};
+}
+
+// largest eigenvalue of a symmetric 3x3: with q = tr/3 and p the scale of
+// M - q 1, the eigenvalues are q + 2 p cos(phi + 2 pi k / 3) with
+// cos(3 phi) = det((M - q 1) / p) / 2 (Smith 1961); k = 0 is the largest
+__device__ __forceinline__ double sym_lambda_max(const Sym3& m) {
+    const double q = (m.a + m.d + m.f) / 3.0;
+    const double a0 = m.a - q, d0 = m.d - q, f0 = m.f - q;
+    const double off = m.b * m.b + m.c * m.c + m.e * m.e;
+    const double p2 = a0 * a0 + d0 * d0 + f0 * f0 + 2.0 * off;
+    if (!(p2 > 0.0)) return q;
+    const double p = sqrt(p2 / 6.0), ip = 1.0 / p;
+    const double ba = a0 * ip, bb = m.b * ip, bc = m.c * ip, bd = d0 * ip, be = m.e * ip, bf = f0 * ip;
+    const double det = ba * (bd * bf - be * be) - bb * (bb * bf - be * bc) + bc * (bb * be - bd * bc);
+    const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+    return q + 2.0 * p * cos(acos(r) / 3.0);
+}
+
+__device__ __forceinline__ void sym_apply(const Sym3& m, double x0, double x1, double x2, double& y0, double& y1,
+                                          double& y2) {
+    y0 = m.a * x0 + m.b * x1 + m.c * x2;
+    y1 = m.b * x0 + m.d * x1 + m.e * x2;
+    y2 = m.c * x0 + m.e * x1 + m.f * x2;
+}
+
+// one block per ring: P_p into ninv6, and the ring's min of alpha_p w_p
+__global__ void tau6_kernel(int64_t npix, const int64_t* __restrict__ roff, const int* __restrict__ rn,
+                            const double* __restrict__ rw, const double* __restrict__ ncov6,
+                            const uint8_t* __restrict__ obs, double* __restrict__ ninv6,
+                            double* __restrict__ ring_min) {
+    __shared__ double sh[kBlk];
+    const int r = blockIdx.x;
+    const int64_t o = roff[r];
+    const int n = rn[r];
+    const double w = rw[r];
+    double v = INFINITY;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int64_t q = o + j;
+        const int m = obs[q];
+        Sym3 P{0, 0, 0, 0, 0, 0};
+        if (m) {
+            P = sym_inverse(load_sym(ncov6, npix, q));
+            if (!(m & 1)) P.a = P.b = P.c = 0.0;
+            if (!(m & 2)) P.b = P.c = P.d = P.e = P.f = 0.0;
+            v = fmin(v, w / sym_lambda_max(P));
+        }
+        store_sym(ninv6, npix, q, P);
+    }
+    v = block_min(v, sh);
+    if (threadIdx.x == 0) ring_min[r] = v;
+}
+
+// grid (nrings): T P
+__global__ void noise6_kernel(int64_t npix, const int64_t* __restrict__ roff, const int* __restrict__ rn,
+                              const double* __restrict__ rw, const double* __restrict__ ninv6, double tau,
+                              double* __restrict__ tn6) {
+    const int r = blockIdx.x;
+    const int64_t o = roff[r];
+    const int n = rn[r];
+    const double T = tau / rw[r];
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        for (int k = 0; k < 6; ++k) tn6[k * npix + o + j] = T * ninv6[k * npix + o + j];
+}
+
+// over (rhs, pixel): d0 = d on observed components, b = T P d0
+__global__ void data6_kernel(int64_t npix, int64_t total, const double* __restrict__ d,
+                             const uint8_t* __restrict__ obs, const double* __restrict__ tn6,
+                             double* __restrict__ d0, double* __restrict__ b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rhs = i / npix, q = i % npix;
+        const int64_t base = rhs * 3 * npix + q;
+        const int m = obs[q];
+        const double x0 = (m & 1) ? d[base] : 0.0;
+        const double x1 = (m & 2) ? d[base + npix] : 0.0;
+        const double x2 = (m & 2) ? d[base + 2 * npix] : 0.0;
+        double y0, y1, y2;
+        sym_apply(load_sym(tn6, npix, q), x0, x1, x2, y0, y1, y2);
+        d0[base] = x0;
+        d0[base + npix] = x1;
+        d0[base + 2 * npix] = x2;
+        b[base] = y0;
+        b[base + npix] = y1;
+        b[base + 2 * npix] = y2;
+    }
+}
+
+// over (rhs, pixel), in place: ux <- t = ux - T P ux + b (eq 9 with the
+// 3x3 K); t_out (nullable) receives a copy
+__global__ void update6_kernel(int64_t npix, int64_t total, double* __restrict__ ux,
+                               const double* __restrict__ tn6, const double* __restrict__ b,
+                               double* __restrict__ t_out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rhs = i / npix, q = i % npix;
+        const int64_t base = rhs * 3 * npix + q;
+        const double x0 = ux[base], x1 = ux[base + npix], x2 = ux[base + 2 * npix];
+        double y0, y1, y2;
+        sym_apply(load_sym(tn6, npix, q), x0, x1, x2, y0, y1, y2);
+        const double t0 = (x0 - y0) + b[base];
+        const double t1 = (x1 - y1) + b[base + npix];
+        const double t2 = (x2 - y2) + b[base + 2 * npix];
+        ux[base] = t0;
+        ux[base + npix] = t1;
+        ux[base + 2 * npix] = t2;
+        if (t_out) {
+            t_out[base] = t0;
+            t_out[base + npix] = t1;
+            t_out[base + 2 * npix] = t2;
+        }
+    }
+}
+
+// grid (nrings, nrhs): ux <- P (ux - d0), b <- P d0,
+// chi_parts[rhs][ring] = sum (d0 - ux)^T P (d0 - ux)
+__global__ void resid6_kernel(int64_t npix, int nrings, const int64_t* __restrict__ roff,
+                              const int* __restrict__ rn, const double* __restrict__ ninv6, double* __restrict__ ux,
+                              const double* __restrict__ d0, double* __restrict__ b, double* __restrict__ chi) {
+    __shared__ double sh[kBlk];
+    const int r = blockIdx.x, rhs = blockIdx.y;
+    const int64_t o = roff[r];
+    const int n = rn[r];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int64_t q = o + j;
+        const int64_t base = (int64_t)rhs * 3 * npix + q;
+        const Sym3 P = load_sym(ninv6, npix, q);
+        const double e0 = ux[base] - d0[base], e1 = ux[base + npix] - d0[base + npix];
+        const double e2 = ux[base + 2 * npix] - d0[base + 2 * npix];
+        double y0, y1, y2, z0, z1, z2;
+        sym_apply(P, e0, e1, e2, y0, y1, y2);
+        sym_apply(P, d0[base], d0[base + npix], d0[base + 2 * npix], z0, z1, z2);
+        acc += e0 * y0 + e1 * y1 + e2 * y2;
+        ux[base] = y0;
+        ux[base + npix] = y1;
+        ux[base + 2 * npix] = y2;
+        b[base] = z0;
+        b[base + npix] = z1;
+        b[base + 2 * npix] = z2;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) chi[(int64_t)rhs * nrings + r] = acc;
 }
 
 // grid (nrings, nrhs): ux <- N^-1 (ux - d0), b <- N^-1 d0,
@@ -189,29 +381,54 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_tau_parts(dm_plan* p, const double* ncov, const uint8_t* obs, double* ring_min, hipStream_t s) {
-    hipLaunchKernelGGL(tau_kernel, dim3(p->nrings), dim3(kBlk), 0, s, p->npix, p->d_ring_off, p->d_ring_n,
-                       p->d_ring_w, ncov, obs, ring_min);
+hipError_t launch_tau_parts(dm_plan* p, const double* ncov, double* ring_min, hipStream_t s) {
+    if (p->ncov_layout == DM_NCOV_SYM6)
+        hipLaunchKernelGGL(tau6_kernel, dim3(p->nrings), dim3(kBlk), 0, s, p->npix, p->d_ring_off, p->d_ring_n,
+                           p->d_ring_w, ncov, p->d_obs, p->d_ninv6, ring_min);
+    else
+        hipLaunchKernelGGL(tau_kernel, dim3(p->nrings), dim3(kBlk), 0, s, p->npix, p->d_ring_off, p->d_ring_n,
+                           p->d_ring_w, ncov, p->d_obs, ring_min);
     return hipGetLastError();
 }
 
-hipError_t launch_noise_setup(dm_plan* p, const double* ncov, const uint8_t* obs, double tau, hipStream_t s) {
-    hipLaunchKernelGGL(noise_kernel, dim3(p->nrings, 3), dim3(kBlk), 0, s, p->npix, p->d_ring_off, p->d_ring_n,
-                       p->d_ring_w, ncov, obs, tau, p->d_K, p->d_tn, p->d_ninv);
+hipError_t launch_noise_setup(dm_plan* p, const double* ncov, double tau, hipStream_t s) {
+    if (p->ncov_layout == DM_NCOV_SYM6)
+        hipLaunchKernelGGL(noise6_kernel, dim3(p->nrings), dim3(kBlk), 0, s, p->npix, p->d_ring_off, p->d_ring_n,
+                           p->d_ring_w, p->d_ninv6, tau, p->d_tn6);
+    else
+        hipLaunchKernelGGL(noise_kernel, dim3(p->nrings, 3), dim3(kBlk), 0, s, p->npix, p->d_ring_off, p->d_ring_n,
+                           p->d_ring_w, ncov, p->d_obs, tau, p->d_K, p->d_tn, p->d_ninv);
     return hipGetLastError();
 }
 
 hipError_t launch_data_setup(dm_plan* p, int nrhs, const double* d, double* d0, double* b, hipStream_t s) {
-    const int64_t total = (int64_t)nrhs * 3 * p->npix;
-    hipLaunchKernelGGL(data_kernel, dim3(grid_for(total)), dim3(kBlk), 0, s, p->npix, total, d, p->d_obs, p->d_tn,
-                       d0, b);
+    if (p->ncov_layout == DM_NCOV_SYM6) {
+        const int64_t total = (int64_t)nrhs * p->npix;
+        hipLaunchKernelGGL(data6_kernel, dim3(grid_for(total)), dim3(kBlk), 0, s, p->npix, total, d, p->d_obs,
+                           p->d_tn6, d0, b);
+    } else {
+        const int64_t total = (int64_t)nrhs * 3 * p->npix;
+        hipLaunchKernelGGL(data_kernel, dim3(grid_for(total)), dim3(kBlk), 0, s, p->npix, total, d, p->d_obs,
+                           p->d_tn, d0, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update6(dm_plan* p, int nrhs, double* ux, const double* b, double* t_out, hipStream_t s) {
+    const int64_t total = (int64_t)nrhs * p->npix;
+    hipLaunchKernelGGL(update6_kernel, dim3(grid_for(total)), dim3(kBlk), 0, s, p->npix, total, ux, p->d_tn6, b,
+                       t_out);
     return hipGetLastError();
 }
 
 hipError_t launch_residual_maps(dm_plan* p, int nrhs, double* ux, const double* d0, double* b, double* chi_parts,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(resid_kernel, dim3(p->nrings, nrhs), dim3(kBlk), 0, s, p->npix, p->nrings, p->d_ring_off,
-                       p->d_ring_n, p->d_ninv, ux, d0, b, chi_parts);
+    if (p->ncov_layout == DM_NCOV_SYM6)
+        hipLaunchKernelGGL(resid6_kernel, dim3(p->nrings, nrhs), dim3(kBlk), 0, s, p->npix, p->nrings,
+                           p->d_ring_off, p->d_ring_n, p->d_ninv6, ux, d0, b, chi_parts);
+    else
+        hipLaunchKernelGGL(resid_kernel, dim3(p->nrings, nrhs), dim3(kBlk), 0, s, p->npix, p->nrings,
+                           p->d_ring_off, p->d_ring_n, p->d_ninv, ux, d0, b, chi_parts);
     return hipGetLastError();
 }
 

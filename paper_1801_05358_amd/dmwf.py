@@ -24,8 +24,9 @@ STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", 
                 -5: "DM_ESTATE", -6: "DM_EUNSUPPORTED"}
 GRID_HEALPIX, GRID_GL = 0, 1
 FP64, MIXED = 0, 1
-NCOV_DIAG3 = 0
-KERNEL_CLASSES = ("legendre_analysis", "legendre_synthesis", "ring_fft_pointwise", "combine_filter")
+NCOV_DIAG3, NCOV_SYM6 = 0, 1
+KERNEL_CLASSES = ("legendre_analysis", "legendre_synthesis", "ring_fft_pointwise", "combine_filter",
+                  "pixel_update_3x3")
 
 
 class DmGrid(ctypes.Structure):
@@ -86,6 +87,8 @@ def lib():
         "dm_alm2map_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
         "dm_alm2map_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
         "dm_map2alm_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+        "dm_set_noise_masks": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
+                                              ctypes.POINTER(ctypes.c_uint8)]),
         "dm_iterate": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]),
         "dm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
         "dm_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]),
@@ -102,7 +105,7 @@ def lib():
 def exported_symbols():
     """Names declared in include/dmwf.h that the binding expects."""
     return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
-            "dm_set_spectra", "dm_set_noise", "dm_set_schedule", "dm_schedule_trace", "dm_wiener_filter",
+            "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_wiener_filter",
             "dm_wiener_filter_device",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
             "dm_map2alm_device", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
@@ -173,13 +176,29 @@ class Plan:
         cl = _f64(cl, (4, self.lmax + 1))
         self._check(lib().dm_set_spectra(self._h, _dptr(cl)))
 
+    def _mask(self, m):
+        if m is None:
+            return None, None
+        m = np.ascontiguousarray(np.asarray(m).astype(np.uint8).reshape(self.npix))
+        return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
     def set_noise(self, ncov, obs=None):
-        ncov = _f64(ncov, (3, self.npix))
-        optr = None
-        if obs is not None:
-            obs = np.ascontiguousarray(np.asarray(obs).astype(np.uint8).reshape(self.npix))
-            optr = obs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-        self._check(lib().dm_set_noise(self._h, _dptr(ncov), NCOV_DIAG3, optr))
+        """ncov [3, npix] (II, QQ, UU) or [6, npix] (II, IQ, IU, QQ, QU, UU);
+        obs None, a common mask [npix], or a pair (obs_t, obs_p) of a
+        temperature and a polarization mask (nonzero = observed)."""
+        ncov = np.asarray(ncov)
+        rows = ncov.shape[0] if ncov.ndim == 2 else 0
+        if rows not in (3, 6):
+            raise ValueError(f"ncov must be [3, npix] or [6, npix], got {ncov.shape}")
+        layout = NCOV_SYM6 if rows == 6 else NCOV_DIAG3
+        ncov = _f64(ncov, (rows, self.npix))
+        if isinstance(obs, (tuple, list)):
+            ot, pt = self._mask(obs[0])
+            op, pp = self._mask(obs[1])
+            self._check(lib().dm_set_noise_masks(self._h, _dptr(ncov), layout, pt, pp))
+        else:
+            o, ptr = self._mask(obs)
+            self._check(lib().dm_set_noise(self._h, _dptr(ncov), layout, ptr))
 
     def set_schedule(self, lambda_start=1e3, nsteps=20, iters_per_step=10):
         """Fixed mode: nsteps cooling steps lambda_start -> 1, iters_per_step each."""

@@ -46,7 +46,7 @@ def test_binding_covers_header():
 
 def test_abi_version(lib):
     lib.dm_abi_version.restype = ctypes.c_int
-    assert lib.dm_abi_version() == 2
+    assert lib.dm_abi_version() == 3
 
 
 def test_no_device_is_reported_cleanly(lib):
