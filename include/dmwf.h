@@ -97,7 +97,13 @@ typedef struct {
  * twice; u_0 = 0; the largest over the right-hand sides of a batch) falls
  * below eps_j = max(eps_end, eps_start * eps_eta^-j), and below eps_end at
  * the last step (the threshold cooling of Sec. 3.2); the solve stops early
- * after max_iters iterations in total.  nsteps is ignored.               */
+ * after max_iters iterations in total.  nsteps is ignored.
+ *
+ * In both modes max_iters > 0 stops a solve once that many iterations
+ * have run in total, counted from the start of the schedule (a resumed
+ * solve counts the iterations before its checkpoint); the solve returns
+ * the iterate reached, and dm_checkpoint_save can record it.  Fixed mode
+ * accepts max_iters = 0 (no cap).                                        */
 typedef struct {
     double lambda_start;   /* >= 1                                          */
     int nsteps;            /* fixed mode: >= 1                              */
@@ -106,7 +112,7 @@ typedef struct {
     double eps_start;      /* epsilon mode: first threshold, >= eps_end     */
     double eps_end;        /* epsilon mode: final threshold, > 0            */
     double eps_eta;        /* epsilon mode: relaxation per step, >= 1       */
-    int max_iters;         /* epsilon mode: cap on the total, >= 1          */
+    int max_iters;         /* cap on the total: >= 1 (epsilon), >= 0 (fixed)*/
 } dm_schedule;
 
 /* Per right-hand side diagnostics.  residual = ||A x - y|| / ||y|| with
@@ -231,6 +237,30 @@ dm_status dm_map2alm_device(dm_plan* plan, int nrhs, const void* map, void* alm,
  * check single iterations step by step.                                  */
 dm_status dm_iterate(dm_plan* plan, int nrhs, const double* d, const double* t_in, double lambda,
                      int niter, double* alm, double* t_out);
+
+/* Checkpoint and resume of a Wiener filter solve.
+ *
+ * dm_checkpoint_save writes the state where the plan's last
+ * dm_wiener_filter / dm_wiener_filter_device call stopped (normally at the
+ * end of the schedule, earlier under a max_iters cap) to the file path:
+ * the iterate u of every RHS (and the one before it in fixed mode), the
+ * iterations done, the cooling step reached, the epsilon-mode trace, the
+ * schedule, and fingerprints of the spectra, the noise and mask, and the
+ * masked data.  The file (versioned, with a checksum) is written to
+ * path + ".tmp" and renamed.  DM_ESTATE if no such solve has completed on
+ * this plan; DM_EINVAL if the file cannot be written.
+ *
+ * dm_checkpoint_load reads such a file into the plan (same grid, lmax and
+ * precision, nrhs <= max_rhs, else DM_EINVAL; a damaged or truncated file
+ * is DM_EINVAL).  The next Wiener filter call then continues from it
+ * instead of starting afresh: it must pass the same nrhs and data, with the
+ * same spectra, noise and mask set and the same schedule except max_iters
+ * (else DM_EINVAL, and the checkpoint stays loaded).  It runs the remaining
+ * iterations (up to the current max_iters) and returns exactly, to the last
+ * bit, what one uninterrupted call would have returned.  The constrained
+ * realization call neither uses nor changes the checkpoint state.       */
+dm_status dm_checkpoint_save(const dm_plan* plan, const char* path);
+dm_status dm_checkpoint_load(dm_plan* plan, const char* path);
 
 /* Per-kernel GPU timing, measured with HIP events on the plan's stream
  * when enabled: enable != 0 turns recording on and clears the totals.

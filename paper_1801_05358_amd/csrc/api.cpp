@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -265,10 +266,42 @@ void sync_plan_stream_to(dm_plan* p, hipStream_t s) {
     HIPCHK(hipEventDestroy(e));
 }
 
+// fingerprint of a device buffer (blocks on s)
+uint64_t device_hash(dm_plan* p, const void* buf, int64_t n, int elem_bytes, hipStream_t s) {
+    uint64_t* acc = reinterpret_cast<uint64_t*>(p->d_red + 8);
+    HIPCHK(hipMemsetAsync(acc, 0, sizeof(uint64_t), s));
+    HIPCHK(launch_hash(buf, n, elem_bytes, acc, s));
+    uint64_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, acc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return hash_mix(h ^ (uint64_t)n);
+}
+
+// the same fingerprint of host doubles
+uint64_t host_hash(const double* x, size_t n) {
+    uint64_t h = 0;
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t v;
+        std::memcpy(&v, x + i, sizeof v);
+        h += hash_mix(v + (uint64_t)i * 0x9E3779B97F4A7C15ull);
+    }
+    return hash_mix(h ^ (uint64_t)n);
+}
+
+// two schedules that produce the same iterates (max_iters only stops early)
+bool same_schedule(const dm_schedule& a, const dm_schedule& b) {
+    if (eps_mode(a) != eps_mode(b) || a.lambda_start != b.lambda_start) return false;
+    if (!eps_mode(a)) return a.nsteps == b.nsteps && a.iters_per_step == b.iters_per_step;
+    return a.beta == b.beta && a.eps_start == b.eps_start && a.eps_end == b.eps_end && a.eps_eta == b.eps_eta;
+}
+
 // The dual messenger solve on device buffers (Algorithm 1).
 //   d: [nrhs][3][npix] device; alm: [nrhs][3][nalm] complex device;
 //   map: nullable device [nrhs][3][npix] (receives Y u).
-void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, hipStream_t s, dm_stats* stats) {
+// resumable: a Wiener filter solve, which continues a loaded checkpoint
+// and leaves its own state for dm_checkpoint_save.
+void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, hipStream_t s, dm_stats* stats,
+               bool resumable) {
     REQUIRE(p->noise_set, DM_ESTATE, "dm_set_noise must be called before solving");
     REQUIRE(p->spectra_set, DM_ESTATE, "dm_set_spectra must be called before solving");
     check_rhs(p, nrhs);
@@ -278,38 +311,73 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     sync_plan_stream_to(p, s);
     const size_t per = (size_t)(p->lmax + 1) * 4;
     const int64_t alm_len = (int64_t)nrhs * 3 * p->nalm * 2;
+    const size_t alm_bytes = (size_t)alm_len * sizeof(double);
+    if (resumable) p->state.valid = false;
 
-    // setup: d0 = mask(d), b = T N^-1 d0, t_0 = d0
+    // setup: d0 = mask(d), b = T N^-1 d0
     HIPCHK(launch_data_setup(p, nrhs, d, p->d_d0, p->d_b, s));
-    ring(p, RING_ANALYSIS, nrhs, p->d_d0, nullptr, nullptr, s);
     const int nsteps = (int)lam.size();
     const bool eps = eps_mode(p->sched);
-    p->trace_cauchy.clear();
-    p->trace_step.clear();
-    int total = 0;
+    const uint64_t hash_data = resumable ? device_hash(p, p->d_d0, (int64_t)nrhs * 3 * p->npix, 8, s) : 0;
+
+    // a loaded checkpoint: the same inputs and schedule, then its iterate
+    dm_plan::Resume* rs = (resumable && p->resume.pending) ? &p->resume : nullptr;
+    if (rs) {
+        REQUIRE(rs->st.nrhs == nrhs, DM_EINVAL,
+                "the loaded checkpoint holds " + std::to_string(rs->st.nrhs) + " right-hand sides, not " +
+                    std::to_string(nrhs));
+        REQUIRE(same_schedule(rs->st.sched, p->sched), DM_EINVAL, "the schedule differs from the checkpoint's");
+        REQUIRE(rs->st.hash_data == hash_data, DM_EINVAL, "the data differ from the checkpoint's");
+        REQUIRE(p->hash_noise == rs->st.hash_noise && p->hash_cl == rs->st.hash_cl, DM_EINVAL,
+                "the noise or the spectra differ from the checkpoint's");
+        HIPCHK(hipMemcpyAsync(alm, rs->u.data(), alm_bytes, hipMemcpyHostToDevice, s));
+        if (rs->has_prev)
+            HIPCHK(hipMemcpyAsync(p->d_alm_prev, rs->uprev.data(), alm_bytes, hipMemcpyHostToDevice, s));
+    }
+    // resuming from u: the ring Fourier data of the next messenger t (or, with
+    // nothing left to run, the final Y u), by the same kernels an
+    // uninterrupted run uses after its analysis, so the result is the same to
+    // the last bit
+    auto restart_from_u = [&](bool final_map) {
+        HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, s));
+        leg_synthesis(p, nrhs, p->d_alm_spin, s);
+        if (final_map)
+            ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+        else
+            messenger_step(p, nrhs, nullptr, s);
+    };
+    if (!rs) {
+        // t_0 = d0; u_0 = 0 (the reference of the first Cauchy ratio)
+        ring(p, RING_ANALYSIS, nrhs, p->d_d0, nullptr, nullptr, s);
+        HIPCHK(hipMemsetAsync(alm, 0, alm_bytes, s));
+    }
     std::vector<double> last_c(nrhs, 0.0);
+    int64_t total = rs ? rs->st.iterations : 0;
+    int next_step = 0;
+    bool finished = false;
     if (!eps) {
         const int niter = p->sched.iters_per_step;
-        total = nsteps * niter;
-        int it = 0;
-        for (int k = 0; k < nsteps; ++k) {
-            const double* F = p->d_filters + per * k;
-            for (int i = 0; i < niter; ++i, ++it) {
-                const bool last = (it == total - 1);
-                if (last && stats) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_len * sizeof(double),
-                                                         hipMemcpyDeviceToDevice, s));
-                // t_hat = A t ; u = F t_hat        (eq 8)
-                leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
-                // u_x = Y u                          (synthesis)
-                leg_synthesis(p, nrhs, p->d_alm_spin, s);
-                if (!last) {
-                    // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
-                    messenger_step(p, nrhs, nullptr, s);
-                } else {
-                    ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
-                }
+        const int64_t full = (int64_t)nsteps * niter;
+        const int64_t end = p->sched.max_iters > 0 ? std::min<int64_t>(full, p->sched.max_iters) : full;
+        if (rs) restart_from_u(total >= end);
+        for (int64_t it = total; it < end; ++it) {
+            const double* F = p->d_filters + per * (it / niter);
+            const bool last = (it == end - 1);
+            // the previous iterate, for the final Cauchy ratio
+            if (last) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
+            // t_hat = A t ; u = F t_hat        (eq 8)
+            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
+            // u_x = Y u                          (synthesis)
+            leg_synthesis(p, nrhs, p->d_alm_spin, s);
+            if (!last) {
+                // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
+                messenger_step(p, nrhs, nullptr, s);
+            } else {
+                ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
             }
         }
+        total = std::max(total, end);
+        finished = total >= full;
     } else {
         // Algorithm 1's loop: per cooling step, repeat until the Cauchy ratio
         // (largest over the RHS) is below that step's threshold.  The ratio
@@ -322,9 +390,22 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
             ~Ev() { if (e) (void)hipEventDestroy(e); }
         } ev;
         HIPCHK(hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
-        HIPCHK(hipMemsetAsync(alm, 0, alm_len * sizeof(double), s));          // u_0 = 0
+        int k0 = 0;
         bool done = false;
-        for (int k = 0; k < nsteps && !done; ++k) {
+        if (rs) {
+            p->trace_cauchy = rs->trace_cauchy;
+            p->trace_step = rs->trace_step;
+            last_c = rs->st.last_c;
+            k0 = rs->st.next_step;
+            finished = rs->st.finished;
+            done = finished || total >= sc.max_iters;
+            restart_from_u(done);
+        } else {
+            p->trace_cauchy.clear();
+            p->trace_step.clear();
+        }
+        next_step = k0;
+        for (int k = k0; k < nsteps && !done; ++k) {
             const double* F = p->d_filters + per * k;
             const double thr = (k == nsteps - 1) ? sc.eps_end
                                                  : std::max(sc.eps_end, sc.eps_start * std::pow(sc.eps_eta, -(double)k));
@@ -347,7 +428,9 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 p->trace_step.push_back(k);
                 ++total;
                 const bool conv = c < thr;
-                if ((conv && k == nsteps - 1) || total >= sc.max_iters) {
+                next_step = conv ? k + 1 : k;
+                finished = conv && k == nsteps - 1;
+                if (finished || total >= sc.max_iters) {
                     ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
                     done = true;
                     break;
@@ -356,6 +439,20 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 if (conv) break;
             }
         }
+    }
+    if (resumable) {
+        // where this solve stopped, for dm_checkpoint_save
+        HIPCHK(hipMemcpyAsync(p->d_state_u, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
+        dm_plan::SolveState& st = p->state;
+        st.nrhs = nrhs;
+        st.iterations = total;
+        st.next_step = next_step;
+        st.finished = finished;
+        st.hash_data = hash_data;
+        st.hash_noise = p->hash_noise;
+        st.hash_cl = p->hash_cl;
+        st.sched = p->sched;
+        st.last_c = last_c;
     }
     // epilogue in FP64 (section a8): a mixed plan recomputes s_x = Y u with
     // the FP64 transforms before it is returned or enters the residual
@@ -393,7 +490,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 for (int k = 0; k < kNormQ; ++k) q[k] += hparts[((size_t)r * nb + b) * kNormQ + k];
             double c = 0;
             for (int j = 0; j < p->nrings; ++j) c += hchi[(size_t)r * p->nrings + j];
-            stats[r].iterations = total;
+            stats[r].iterations = (int)total;
             stats[r].cauchy = eps ? last_c[r] : (q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0);
             stats[r].residual = q[3] > 0 ? std::sqrt(q[2] / q[3]) : 0.0;
             stats[r].chi2 = c + q[4];
@@ -405,6 +502,8 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     }
     if (p->profiling) collect_events(p);
     REQUIRE(cnt == 0, DM_ENONFINITE, "the iterate became non-finite");
+    if (rs) p->resume = dm_plan::Resume();
+    if (resumable) p->state.valid = true;
 }
 
 void free_plan(dm_plan* p) {
@@ -419,7 +518,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
     dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
-    dfree(p->d_ninv6); dfree(p->d_tn6);
+    dfree(p->d_ninv6); dfree(p->d_tn6); dfree(p->d_state_u);
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
     dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
@@ -636,6 +735,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         dalloc(p, p->d_partial, slots * B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_prev, B * 3 * p->nalm * 2);
+        dalloc(p, p->d_state_u, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_spin, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_r, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_y, B * 3 * p->nalm * 2);
@@ -705,6 +805,7 @@ dm_status dm_set_spectra(dm_plan* p, const double* cl) {
         all.insert(all.end(), m3.begin(), m3.end());
         upload(p, p->d_mats, all.data(), all.size());
         HIPCHK(hipStreamSynchronize(p->stream));
+        p->hash_cl = host_hash(p->cl.data(), p->cl.size());
         p->spectra_set = true;
     });
 }
@@ -771,7 +872,11 @@ dm_status dm_set_noise_masks(dm_plan* p, const double* ncov, dm_ncov layout, con
         REQUIRE(std::isfinite(tau) && tau > 0, DM_EINVAL, "no valid observed pixel");
         p->tau = tau;
         HIPCHK(launch_noise_setup(p, d_ncov, tau, p->stream));
-        HIPCHK(hipStreamSynchronize(p->stream));
+        // fingerprint: the mask bits and T N^-1 (which carries tau)
+        const bool sym = layout == DM_NCOV_SYM6;
+        const uint64_t h_obs = device_hash(p, p->d_obs, n, 1, p->stream);
+        const uint64_t h_tn = device_hash(p, sym ? p->d_tn6 : p->d_tn, (sym ? 6 : 3) * n, 8, p->stream);
+        p->hash_noise = hash_mix(h_obs + 3 * hash_mix(h_tn + (uint64_t)layout));
         p->noise_set = true;
     });
 }
@@ -783,6 +888,7 @@ dm_status dm_set_schedule(dm_plan* p, const dm_schedule* sc) {
         if (sc->iters_per_step >= 1) {
             REQUIRE(sc->nsteps >= 1 && sc->nsteps <= 100000, DM_EINVAL, "nsteps must be in [1, 100000]");
             REQUIRE(sc->iters_per_step <= 10000000, DM_EINVAL, "iters_per_step must be <= 1e7");
+            REQUIRE(sc->max_iters >= 0, DM_EINVAL, "max_iters must be >= 0 (0: no cap)");
         } else {
             REQUIRE(std::isfinite(sc->beta) && sc->beta > 0.0 && sc->beta < 1.0, DM_EINVAL,
                     "epsilon mode: beta must be in (0, 1)");
@@ -796,6 +902,209 @@ dm_status dm_set_schedule(dm_plan* p, const dm_schedule* sc) {
                     "epsilon mode: more than 1e5 cooling steps");
         }
         p->sched = *sc;
+    });
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// checkpoint files: a fixed little header, the state, and a checksum of
+// every byte before it.  Written to path + ".tmp", then renamed.
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr char kCkMagic[8] = {'D', 'M', 'W', 'F', 'C', 'K', 'P', 'T'};
+constexpr uint32_t kCkVersion = 1;
+
+struct CkSum {
+    uint64_t h = 0x6A09E667F3BCC909ull;
+    void add(const void* buf, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(buf);
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t w;
+            std::memcpy(&w, b + i, 8);
+            h = dmwf::hash_mix(h ^ w);
+        }
+        uint64_t w = 0;
+        std::memcpy(&w, b + i, n - i);
+        h = dmwf::hash_mix(h ^ w ^ ((uint64_t)(n - i) << 56));
+    }
+};
+
+struct CkWriter {
+    std::FILE* f;
+    CkSum sum;
+    bool ok = true;
+    void put(const void* buf, size_t n) {
+        sum.add(buf, n);
+        if (n && std::fwrite(buf, 1, n, f) != n) ok = false;
+    }
+    template <typename T>
+    void val(T v) { put(&v, sizeof v); }
+};
+
+struct CkReader {
+    std::FILE* f;
+    CkSum sum;
+    bool ok = true;
+    void get(void* buf, size_t n) {
+        if (n && std::fread(buf, 1, n, f) != n) {
+            ok = false;
+            std::memset(buf, 0, n);
+        }
+        sum.add(buf, n);
+    }
+    template <typename T>
+    T val() {
+        T v;
+        get(&v, sizeof v);
+        return v;
+    }
+};
+
+void put_schedule(CkWriter& w, const dm_schedule& sc) {
+    w.val(sc.lambda_start);
+    w.val<int32_t>(sc.nsteps);
+    w.val<int32_t>(sc.iters_per_step);
+    w.val(sc.beta);
+    w.val(sc.eps_start);
+    w.val(sc.eps_end);
+    w.val(sc.eps_eta);
+    w.val<int32_t>(sc.max_iters);
+}
+
+dm_schedule get_schedule(CkReader& r) {
+    dm_schedule sc{};
+    sc.lambda_start = r.val<double>();
+    sc.nsteps = r.val<int32_t>();
+    sc.iters_per_step = r.val<int32_t>();
+    sc.beta = r.val<double>();
+    sc.eps_start = r.val<double>();
+    sc.eps_end = r.val<double>();
+    sc.eps_eta = r.val<double>();
+    sc.max_iters = r.val<int32_t>();
+    return sc;
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_checkpoint_save(const dm_plan* cp, const char* path) {
+    dm_plan* p = const_cast<dm_plan*>(cp);
+    return guarded(p, [&] {
+        REQUIRE(path != nullptr && path[0], DM_EINVAL, "path is empty");
+        REQUIRE(p->state.valid, DM_ESTATE, "no completed Wiener filter solve to checkpoint");
+        const dm_plan::SolveState& st = p->state;
+        const bool eps = eps_mode(st.sched);
+        const size_t n = (size_t)st.nrhs * 3 * p->nalm * 2;
+        std::vector<double> u(n), up;
+        HIPCHK(hipMemcpyAsync(u.data(), p->d_state_u, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        if (!eps) {
+            up.resize(n);
+            HIPCHK(hipMemcpyAsync(up.data(), p->d_alm_prev, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        }
+        HIPCHK(hipStreamSynchronize(p->stream));
+        const std::string tmp = std::string(path) + ".tmp";
+        std::FILE* f = std::fopen(tmp.c_str(), "wb");
+        REQUIRE(f != nullptr, DM_EINVAL, "cannot open " + tmp + " for writing");
+        CkWriter w{f};
+        w.put(kCkMagic, sizeof kCkMagic);
+        w.val<uint32_t>(kCkVersion);
+        w.val<int32_t>(p->grid.kind);
+        w.val<int32_t>(p->grid.nside);
+        w.val<int32_t>(p->grid.ntheta);
+        w.val<int32_t>(p->grid.nphi);
+        w.val<int32_t>(p->lmax);
+        w.val<int32_t>(p->precision);
+        w.val<int32_t>(p->ncov_layout);
+        w.val<int32_t>(st.nrhs);
+        w.val<int64_t>(p->nalm);
+        put_schedule(w, st.sched);
+        w.val<uint64_t>(st.hash_cl);
+        w.val<uint64_t>(st.hash_noise);
+        w.val<uint64_t>(st.hash_data);
+        w.val<int64_t>(st.iterations);
+        w.val<int32_t>(st.next_step);
+        w.val<int32_t>(st.finished ? 1 : 0);
+        w.val<int32_t>(eps ? 0 : 1);
+        const std::vector<double>& tc = p->trace_cauchy;
+        const std::vector<int>& ts = p->trace_step;
+        const int64_t ntr = eps ? (int64_t)tc.size() : 0;
+        w.val<int64_t>(ntr);
+        for (int64_t i = 0; i < ntr; ++i) w.val<double>(tc[i]);
+        for (int64_t i = 0; i < ntr; ++i) w.val<int32_t>(ts[i]);
+        for (int r = 0; r < st.nrhs; ++r) w.val<double>(r < (int)st.last_c.size() ? st.last_c[r] : 0.0);
+        w.put(u.data(), n * sizeof(double));
+        if (!eps) w.put(up.data(), n * sizeof(double));
+        const uint64_t sum = w.sum.h;
+        if (std::fwrite(&sum, sizeof sum, 1, f) != 1) w.ok = false;
+        if (std::fclose(f) != 0) w.ok = false;
+        if (!w.ok) std::remove(tmp.c_str());
+        REQUIRE(w.ok, DM_EINVAL, "writing " + tmp + " failed");
+        REQUIRE(std::rename(tmp.c_str(), path) == 0, DM_EINVAL, std::string("cannot rename to ") + path);
+    });
+}
+
+dm_status dm_checkpoint_load(dm_plan* p, const char* path) {
+    return guarded(p, [&] {
+        REQUIRE(path != nullptr && path[0], DM_EINVAL, "path is empty");
+        std::FILE* f = std::fopen(path, "rb");
+        REQUIRE(f != nullptr, DM_EINVAL, std::string("cannot open ") + path);
+        std::unique_ptr<std::FILE, int (*)(std::FILE*)> guard(f, &std::fclose);
+        CkReader r{f};
+        char magic[8];
+        r.get(magic, sizeof magic);
+        REQUIRE(r.ok && std::memcmp(magic, kCkMagic, 8) == 0, DM_EINVAL, "not a checkpoint file");
+        REQUIRE(r.val<uint32_t>() == kCkVersion, DM_EINVAL, "unsupported checkpoint version");
+        const int kind = r.val<int32_t>(), nside = r.val<int32_t>(), ntheta = r.val<int32_t>(),
+                  nphi = r.val<int32_t>(), lmax = r.val<int32_t>(), prec = r.val<int32_t>();
+        (void)r.val<int32_t>();                          // noise layout (part of the noise fingerprint)
+        const int nrhs = r.val<int32_t>();
+        const int64_t nalm = r.val<int64_t>();
+        REQUIRE(r.ok, DM_EINVAL, "truncated checkpoint");
+        const bool same_grid = kind == p->grid.kind &&
+                               (kind == DM_GRID_HEALPIX_RING ? nside == p->grid.nside
+                                                             : (ntheta == p->grid.ntheta && nphi == p->grid.nphi));
+        REQUIRE(same_grid && lmax == p->lmax && nalm == p->nalm, DM_EINVAL,
+                "the checkpoint was written for another grid or lmax");
+        REQUIRE(prec == p->precision, DM_EINVAL, "the checkpoint was written with another precision");
+        REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, DM_EINVAL, "the checkpoint holds more RHS than max_rhs");
+        dm_plan::Resume rs;
+        dm_plan::SolveState& st = rs.st;
+        st.nrhs = nrhs;
+        st.sched = get_schedule(r);
+        st.hash_cl = r.val<uint64_t>();
+        st.hash_noise = r.val<uint64_t>();
+        st.hash_data = r.val<uint64_t>();
+        st.iterations = r.val<int64_t>();
+        st.next_step = r.val<int32_t>();
+        st.finished = r.val<int32_t>() != 0;
+        rs.has_prev = r.val<int32_t>() != 0;
+        const int64_t ntr = r.val<int64_t>();
+        REQUIRE(r.ok && st.iterations >= 0 && st.iterations <= 100000000 && ntr >= 0 && ntr <= st.iterations &&
+                    st.next_step >= 0 && rs.has_prev == !eps_mode(st.sched),
+                DM_EINVAL, "corrupt checkpoint header");
+        rs.trace_cauchy.resize(ntr);
+        rs.trace_step.resize(ntr);
+        for (int64_t i = 0; i < ntr; ++i) rs.trace_cauchy[i] = r.val<double>();
+        for (int64_t i = 0; i < ntr; ++i) rs.trace_step[i] = r.val<int32_t>();
+        st.last_c.resize(nrhs);
+        for (int k = 0; k < nrhs; ++k) st.last_c[k] = r.val<double>();
+        const size_t n = (size_t)nrhs * 3 * p->nalm * 2;
+        rs.u.resize(n);
+        r.get(rs.u.data(), n * sizeof(double));
+        if (rs.has_prev) {
+            rs.uprev.resize(n);
+            r.get(rs.uprev.data(), n * sizeof(double));
+        }
+        const uint64_t want = r.sum.h;
+        uint64_t sum = 0;
+        REQUIRE(r.ok && std::fread(&sum, sizeof sum, 1, f) == 1, DM_EINVAL, "truncated checkpoint");
+        REQUIRE(sum == want, DM_EINVAL, "checkpoint checksum mismatch");
+        rs.pending = true;
+        p->resume = std::move(rs);
     });
 }
 
@@ -824,7 +1133,7 @@ dm_status dm_wiener_filter(dm_plan* p, int nrhs, const double* d, double* alm, d
         if (map) HIPCHK(hipMalloc((void**)&dm, nmap * sizeof(double)));
         std::unique_ptr<double, decltype(del)> g3(dm, del);
         upload(p, dd, d, nmap);
-        solve_dev(p, nrhs, dd, da, dm, p->stream, stats);
+        solve_dev(p, nrhs, dd, da, dm, p->stream, stats, true);
         HIPCHK(hipMemcpyAsync(alm, da, (size_t)nrhs * 3 * p->nalm * 2 * sizeof(double), hipMemcpyDeviceToHost,
                               p->stream));
         if (map) HIPCHK(hipMemcpyAsync(map, dm, nmap * sizeof(double), hipMemcpyDeviceToHost, p->stream));
@@ -847,7 +1156,7 @@ dm_status dm_wiener_filter_device(dm_plan* p, int nrhs, const void* d, void* alm
         HIPCHK(hipMemcpyAsync(&cnt, d_cnt, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         REQUIRE(cnt == 0, DM_EINVAL, "d must be finite");
-        solve_dev(p, nrhs, (const double*)d, (double*)alm, (double*)map, s, stats);
+        solve_dev(p, nrhs, (const double*)d, (double*)alm, (double*)map, s, stats, true);
     });
 }
 
@@ -875,7 +1184,7 @@ dm_status dm_constrained_realizations(dm_plan* p, int nreal, const double* d, co
         for (int k = 0; k < nreal; ++k)
             HIPCHK(launch_axpby(dd + nm * (k + 1), dd, 1.0, -1.0, (int64_t)nm, p->stream));
         upload(p, ds, shat_alm, na * nreal);
-        solve_dev(p, B, dd, da, nullptr, p->stream, nullptr);
+        solve_dev(p, B, dd, da, nullptr, p->stream, nullptr, false);
         // s_CR,k = W(d - d_hat_k) + s_hat_k
         HIPCHK(launch_axpby(da + na, ds, 1.0, 1.0, (int64_t)(na * nreal), p->stream));
         HIPCHK(hipMemcpyAsync(scr_alm, da + na, na * nreal * sizeof(double), hipMemcpyDeviceToHost, p->stream));

@@ -155,6 +155,32 @@ struct dm_plan {
     std::vector<double> trace_cauchy;
     std::vector<int> trace_step;
 
+    // input fingerprints (checked when a solve resumes from a checkpoint)
+    uint64_t hash_cl = 0, hash_noise = 0;
+    // where the last Wiener filter solve stopped: its iterate u in d_state_u,
+    // the one before it in d_alm_prev (fixed mode), the position in the
+    // schedule and the fingerprint of its masked data
+    struct SolveState {
+        bool valid = false;
+        int nrhs = 0;
+        int64_t iterations = 0;        // completed, counted from the schedule's start
+        int next_step = 0;             // epsilon mode: cooling step of the next iteration
+        bool finished = false;         // the schedule ran to its end
+        uint64_t hash_data = 0, hash_noise = 0, hash_cl = 0;
+        dm_schedule sched{};
+        std::vector<double> last_c;    // epsilon mode: last Cauchy ratio per RHS
+    } state;
+    double* d_state_u = nullptr;       // [B][3][nalm] complex
+    // a loaded checkpoint, consumed by the next Wiener filter solve
+    struct Resume {
+        bool pending = false;
+        SolveState st;
+        std::vector<double> trace_cauchy;
+        std::vector<int> trace_step;
+        std::vector<double> u, uprev;  // [nrhs][3][nalm][2]
+        bool has_prev = false;
+    } resume;
+
     // timing
     bool profiling = false;
     double kc_ms[dmwf::KC_COUNT] = {0, 0, 0, 0, 0};
@@ -222,6 +248,11 @@ hipError_t launch_update6(dm_plan* p, int nrhs, double* ux, const double* b, dou
 // chi_parts [nrhs][nrings] = sum (d0-ux)^T N^-1 (d0-ux)
 hipError_t launch_residual_maps(dm_plan* p, int nrhs, double* ux, const double* d0, double* b,
                                 double* chi_parts, hipStream_t s);
+// fingerprint of a buffer of n elements of elem_bytes (1 or 8) bytes:
+// sum over i of mix(v_i + i g) mod 2^64, accumulated into *acc (which the
+// caller zeroes); integer sums, so the value does not depend on the order
+hipError_t launch_hash(const void* buf, int64_t n, int elem_bytes, uint64_t* acc, hipStream_t s);
+uint64_t hash_mix(uint64_t x);
 // per (rhs, m, block) sums: |u-uprev|^2, |u|^2, |r|^2, |y|^2, u^T S^+ u
 constexpr int kNormQ = 5;
 int alm_norm_blocks(dm_plan* p);

@@ -227,28 +227,30 @@ __global__ void data6_kernel(int64_t npix, int64_t total, const double* __restri
     }
 }
 
-// over (rhs, pixel), in place: ux <- t = ux - T P ux + b (eq 9 with the
-// 3x3 K); t_out (nullable) receives a copy
-__global__ void update6_kernel(int64_t npix, int64_t total, double* __restrict__ ux,
-                               const double* __restrict__ tn6, const double* __restrict__ b,
-                               double* __restrict__ t_out) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t rhs = i / npix, q = i % npix;
-        const int64_t base = rhs * 3 * npix + q;
-        const double x0 = ux[base], x1 = ux[base + npix], x2 = ux[base + 2 * npix];
-        double y0, y1, y2;
-        sym_apply(load_sym(tn6, npix, q), x0, x1, x2, y0, y1, y2);
-        const double t0 = (x0 - y0) + b[base];
-        const double t1 = (x1 - y1) + b[base + npix];
-        const double t2 = (x2 - y2) + b[base + 2 * npix];
-        ux[base] = t0;
-        ux[base + npix] = t1;
-        ux[base + 2 * npix] = t2;
-        if (t_out) {
-            t_out[base] = t0;
-            t_out[base + npix] = t1;
-            t_out[base + 2 * npix] = t2;
+// over pixels, in place: ux <- t = ux - T P ux + b (eq 9 with the 3x3 K)
+// for every RHS; t_out (nullable) receives a copy.  T P is read once per
+// pixel for all RHS.
+__global__ void update6_kernel(int64_t npix, int nrhs, double* __restrict__ ux, const double* __restrict__ tn6,
+                               const double* __restrict__ b, double* __restrict__ t_out) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < npix;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const Sym3 M = load_sym(tn6, npix, q);
+        for (int rhs = 0; rhs < nrhs; ++rhs) {
+            const int64_t base = (int64_t)rhs * 3 * npix + q;
+            const double x0 = ux[base], x1 = ux[base + npix], x2 = ux[base + 2 * npix];
+            double y0, y1, y2;
+            sym_apply(M, x0, x1, x2, y0, y1, y2);
+            const double t0 = (x0 - y0) + b[base];
+            const double t1 = (x1 - y1) + b[base + npix];
+            const double t2 = (x2 - y2) + b[base + 2 * npix];
+            ux[base] = t0;
+            ux[base + npix] = t1;
+            ux[base + 2 * npix] = t2;
+            if (t_out) {
+                t_out[base] = t0;
+                t_out[base + npix] = t1;
+                t_out[base + 2 * npix] = t2;
+            }
         }
     }
 }
@@ -372,6 +374,37 @@ __global__ void axpby_kernel(double* __restrict__ y, const double* __restrict__ 
         y[i] = a * x[i] + c * y[i];
 }
 
+// SplitMix64's output function (Steele, Lea and Flood 2014), as the
+// per-element mix of the buffer fingerprints
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename E>
+__global__ void hash_kernel(const E* __restrict__ x, int64_t n, unsigned long long* __restrict__ acc) {
+    __shared__ unsigned long long sh[kBlk];
+    unsigned long long h = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t v;
+        if constexpr (sizeof(E) == 8) {
+            v = reinterpret_cast<const uint64_t*>(x)[i];
+        } else {
+            v = (uint64_t)x[i];
+        }
+        h += mix64(v + (uint64_t)i * 0x9E3779B97F4A7C15ull);
+    }
+    const int tid = threadIdx.x;
+    sh[tid] = h;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (tid < o) sh[tid] += sh[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) atomicAdd(acc, sh[0]);
+}
+
 int grid_for(int64_t n) {
     int64_t g = (n + kBlk - 1) / kBlk;
     if (g > 65536) g = 65536;
@@ -415,8 +448,7 @@ hipError_t launch_data_setup(dm_plan* p, int nrhs, const double* d, double* d0, 
 }
 
 hipError_t launch_update6(dm_plan* p, int nrhs, double* ux, const double* b, double* t_out, hipStream_t s) {
-    const int64_t total = (int64_t)nrhs * p->npix;
-    hipLaunchKernelGGL(update6_kernel, dim3(grid_for(total)), dim3(kBlk), 0, s, p->npix, total, ux, p->d_tn6, b,
+    hipLaunchKernelGGL(update6_kernel, dim3(grid_for(p->npix)), dim3(kBlk), 0, s, p->npix, nrhs, ux, p->d_tn6, b,
                        t_out);
     return hipGetLastError();
 }
@@ -429,6 +461,20 @@ hipError_t launch_residual_maps(dm_plan* p, int nrhs, double* ux, const double* 
     else
         hipLaunchKernelGGL(resid_kernel, dim3(p->nrings, nrhs), dim3(kBlk), 0, s, p->npix, p->nrings,
                            p->d_ring_off, p->d_ring_n, p->d_ninv, ux, d0, b, chi_parts);
+    return hipGetLastError();
+}
+
+uint64_t hash_mix(uint64_t x) { return mix64(x); }
+
+hipError_t launch_hash(const void* buf, int64_t n, int elem_bytes, uint64_t* acc, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    unsigned long long* a = reinterpret_cast<unsigned long long*>(acc);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(hash_kernel<uint64_t>, dim3(grid_for(n)), dim3(kBlk), 0, s,
+                           reinterpret_cast<const uint64_t*>(buf), n, a);
+    else
+        hipLaunchKernelGGL(hash_kernel<uint8_t>, dim3(grid_for(n)), dim3(kBlk), 0, s,
+                           reinterpret_cast<const uint8_t*>(buf), n, a);
     return hipGetLastError();
 }
 

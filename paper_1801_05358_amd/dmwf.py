@@ -89,6 +89,8 @@ def lib():
         "dm_map2alm_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
         "dm_set_noise_masks": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
                                               ctypes.POINTER(ctypes.c_uint8)]),
+        "dm_checkpoint_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+        "dm_checkpoint_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "dm_iterate": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]),
         "dm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
         "dm_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]),
@@ -108,7 +110,7 @@ def exported_symbols():
             "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_wiener_filter",
             "dm_wiener_filter_device",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
-            "dm_map2alm_device", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
+            "dm_map2alm_device", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
 
 
 def device_count():
@@ -200,9 +202,11 @@ class Plan:
             o, ptr = self._mask(obs)
             self._check(lib().dm_set_noise(self._h, _dptr(ncov), layout, ptr))
 
-    def set_schedule(self, lambda_start=1e3, nsteps=20, iters_per_step=10):
-        """Fixed mode: nsteps cooling steps lambda_start -> 1, iters_per_step each."""
-        s = DmSchedule(float(lambda_start), int(nsteps), int(iters_per_step), 0.0, 0.0, 0.0, 0.0, 0)
+    def set_schedule(self, lambda_start=1e3, nsteps=20, iters_per_step=10, max_iters=0):
+        """Fixed mode: nsteps cooling steps lambda_start -> 1, iters_per_step
+        each; max_iters > 0 stops a solve after that many iterations in
+        total (it can be resumed from a checkpoint)."""
+        s = DmSchedule(float(lambda_start), int(nsteps), int(iters_per_step), 0.0, 0.0, 0.0, 0.0, int(max_iters))
         self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
 
     def set_schedule_eps(self, lambda_start=1e3, beta=0.75, eps_start=1e-4, eps_end=1e-6, eta=1.1,
@@ -211,6 +215,14 @@ class Plan:
         s = DmSchedule(float(lambda_start), 0, 0, float(beta), float(eps_start), float(eps_end), float(eta),
                        int(max_iters))
         self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
+
+    def checkpoint_save(self, path):
+        """Write where the last Wiener filter solve stopped to path."""
+        self._check(lib().dm_checkpoint_save(self._h, os.fsencode(path)))
+
+    def checkpoint_load(self, path):
+        """Load a checkpoint; the next Wiener filter call continues from it."""
+        self._check(lib().dm_checkpoint_load(self._h, os.fsencode(path)))
 
     def schedule_trace(self):
         """(cauchy [n], step [n]) of the last epsilon-mode solve."""
