@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--lmax", type=int, default=2048)
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--noise", choices=["diag", "corr"], default="diag",
+                    help="diag: diagonal noise, one mask; corr: correlated 3x3 noise with distinct T and P masks")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 reference solve and baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -218,14 +220,20 @@ def main():
     nside, lmax, B = args.nside, args.lmax, args.nrhs
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"[bench] workload nside={nside} lmax={lmax} nrhs={B} precision={args.precision}")
-    prob = inputs.make_problem(3, nside=nside, lmax=lmax)
+    corr = args.noise == "corr"
+    if corr:
+        prob = inputs.correlated_problem(3, nside=nside, lmax=lmax)
+        ncov, obs = prob["ncov6"], (prob["obs_t"], prob["obs_p"])
+    else:
+        prob = inputs.make_problem(3, nside=nside, lmax=lmax)
+        ncov, obs = prob["ncov"], prob["obs"]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
     def make_plan(prec, nrhs):
         plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=nrhs, device=0, precision=prec)
         plan.set_spectra(prob["cl"])
-        plan.set_noise(prob["ncov"], prob["obs"])
+        plan.set_noise(ncov, obs)
         return plan
 
     def set_iters(plan, k):
@@ -241,7 +249,8 @@ def main():
     alm_t = torch.from_numpy(s.view(np.float64).reshape(B, 3, -1)).to(dev)
     d_t = torch.empty((B, 3, plan.npix), dtype=torch.float64, device=dev)
     plan.alm2map_device(alm_t, d_t, stream=stream)
-    noise = np.stack([inputs.noise_map(3, prob["ncov"], prob["obs"], k) for k in range(B)])
+    noise = np.stack([inputs.noise_map6(3, ncov, prob["obs3"], k) if corr else inputs.noise_map(3, ncov, obs, k)
+                      for k in range(B)])
     d_t += torch.from_numpy(noise).to(dev)
     del noise
     out_t = torch.empty((B, 3, plan.nalm * 2), dtype=torch.float64, device=dev)
@@ -289,10 +298,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"HEALPix Nside {nside}, lmax {lmax}, mask |b|<15 deg + 1000 holes of 0.5 deg, "
-                               f"scan noise 100:1 (Q = U = 2 T), cooling lambda 1e3 -> 1 in steps of 10 "
+        "config": {"workload": f"HEALPix Nside {nside}, lmax {lmax}, " + (
+                               "T mask |b|<15 deg + 2000 holes, P mask |b|<12 deg + 1000 other holes, "
+                               "correlated 3x3 scan noise 100:1 (Q = U = 2 T, correlations .3/-.15/.2), "
+                               if corr else
+                               "mask |b|<15 deg + 1000 holes of 0.5 deg, scan noise 100:1 (Q = U = 2 T), ") +
+                               f"cooling lambda 1e3 -> 1 in steps of 10 "
                                f"iterations, {B} right-hand sides per launch ({prec_text})",
-                   "nside": nside, "lmax": lmax, "nrhs": B, "precision": args.precision},
+                   "nside": nside, "lmax": lmax, "nrhs": B, "precision": args.precision, "noise": args.noise},
         "solve_iterations_per_s": round(its, 4),
         "rhs_iterations_per_s": round(B * its, 3),
         "roofline": {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak,

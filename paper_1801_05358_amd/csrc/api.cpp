@@ -157,6 +157,10 @@ bool use_mfma(dm_plan* p, int nrhs) {
     return nrhs >= (p->precision == DM_MIXED ? 2 : 8);
 }
 
+// the batched kernels carry scaled recursions; their scales enter the
+// combine step and the spin-basis copy
+const double* spin_scales(dm_plan* p, int nrhs) { return use_mfma(p, nrhs) ? p->d_scale : nullptr; }
+
 void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, double* alm, double* spin,
                   hipStream_t s, double* cpart = nullptr) {
     const void* phase = phase_of(p, nrhs);
@@ -174,7 +178,7 @@ void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, dou
         t.done();
     }
     Timed t(p, KC_COMBINE, s);
-    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, filter, alm, spin, cpart, s));
+    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, filter, alm, spin, cpart, spin_scales(p, nrhs), s));
     t.done();
 }
 
@@ -198,7 +202,7 @@ void map2alm_dev(dm_plan* p, int nrhs, const double* map, double* alm, bool weig
 }
 
 void alm2map_dev(dm_plan* p, int nrhs, const double* alm, double* map, hipStream_t s) {
-    HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, s));
+    HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, spin_scales(p, nrhs), s));
     leg_synthesis(p, nrhs, p->d_alm_spin, s);
     ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, s);
 }
@@ -339,7 +343,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     // uninterrupted run uses after its analysis, so the result is the same to
     // the last bit
     auto restart_from_u = [&](bool final_map) {
-        HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, s));
+        HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, spin_scales(p, nrhs), s));
         leg_synthesis(p, nrhs, p->d_alm_spin, s);
         if (final_map)
             ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
@@ -516,7 +520,7 @@ void free_plan(dm_plan* p) {
     }
     dfree(p->d_pair_x); dfree(p->d_pair_w); dfree(p->d_pair_one); dfree(p->d_pairs); dfree(p->d_fftlen);
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
-    dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_lstart); dfree(p->d_seed);
+    dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_coef_s); dfree(p->d_scale); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
     dfree(p->d_ninv6); dfree(p->d_tn6); dfree(p->d_state_u);
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
@@ -690,6 +694,15 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         dalloc(p, p->d_lp0, lp0.size());
         dalloc(p, p->d_lp2, lp2.size());
         upload(p, p->d_coef, coef.data(), coef.size());
+        {
+            std::vector<double> coef_s, scale;
+            build_scaled_coefficients(lmax, coef_s, scale);
+            dalloc(p, p->d_coef_s, coef_s.size());
+            dalloc(p, p->d_scale, scale.size());
+            upload(p, p->d_coef_s, coef_s.data(), coef_s.size());
+            upload(p, p->d_scale, scale.data(), scale.size());
+            HIPCHK(hipStreamSynchronize(p->stream));
+        }
         upload(p, p->d_lp0, lp0.data(), lp0.size());
         upload(p, p->d_lp2, lp2.data(), lp2.size());
         const size_t sn = (size_t)(p->mmax + 1) * p->npairs;

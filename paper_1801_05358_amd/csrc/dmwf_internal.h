@@ -15,6 +15,7 @@ namespace dmwf {
 // Recursion coefficients per packed (l, m), producing the value at l from
 // the values at l-1 and l-2 (see legendre.hip).
 constexpr int kCoefStride = 6;   // A0, B0, alpha, alpha*beta, gamma, pad
+constexpr int kCoefSStride = 4;  // scaled recursions: A0', alpha', (alpha*beta)', pad
 
 // Per-(m, ring pair) recursion seeds: values at (ls-1, ls) of
 // lam, (+2)lam, (-2)lam (for m < 2 the spin-2 slots hold l = 1, 2).
@@ -95,6 +96,8 @@ struct dm_plan {
     float* d_bhat32 = nullptr;
     float* d_tw32 = nullptr;
     double* d_coef = nullptr;          // [nalm][kCoefStride]
+    double* d_coef_s = nullptr;        // [nalm][kCoefSStride] scaled recursions (batched kernels)
+    double* d_scale = nullptr;         // [nalm][2] their scales S (spin 0, spin 2)
     int* d_lstart = nullptr;           // [mmax+1][npairs]
     double* d_seed = nullptr;          // [kSeedFields][mmax+1][npairs]
     double* d_lp0 = nullptr;           // [mmax+1] log seed prefactors, spin 0
@@ -192,6 +195,7 @@ namespace dmwf {
 
 // tables.cpp
 bool build_rings(const dm_grid& g, RingTables& rt, int64_t& npix, std::string& err);
+void build_scaled_coefficients(int lmax, std::vector<double>& coef_s, std::vector<double>& scale);
 void build_coefficients(int lmax, std::vector<double>& coef, std::vector<double>& lp0,
                         std::vector<double>& lp2);
 bool build_fft_tables(const RingTables& rt, int mmax, FftTables& ft, std::string& err);
@@ -207,11 +211,14 @@ hipError_t launch_leg_synthesis(dm_plan* p, int nrhs, const double* spin_alm, do
 // writes the spin-basis copy for the next synthesis (spin may be null).
 hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const double* pair_w,
                                double* partial, hipStream_t s);
+// scale (nullable): the batched kernels' recursion scales, applied to the
+// partial sums and to the spin-basis copy
 hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
-                          double* alm, double* spin, double* cpart, hipStream_t s);
+                          double* alm, double* spin, double* cpart, const double* scale, hipStream_t s);
 int64_t cauchy_blocks(dm_plan* p);   // Cauchy partial sums per RHS written by the combine kernel
 hipError_t launch_cauchy_reduce(dm_plan* p, int nrhs, const double* cpart, double* out, hipStream_t s);
-hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s);
+hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, const double* scale,
+                          hipStream_t s);
 void set_analysis_tiling(dm_plan* p, int R);
 
 // legendre_mfma.hip: batched Legendre products on the matrix cores

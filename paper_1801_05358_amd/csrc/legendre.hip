@@ -499,6 +499,15 @@ __device__ __forceinline__ void eb_to_spin(double2 e, double2 b, double2& p2, do
     m2 = make_double2(-(e.x + b.y), -(e.y - b.x));
 }
 
+// the spin-basis copy (T, (2)a, (-2)a), each times its recursion scale
+// (1 for the vector kernels)
+__device__ __forceinline__ void spin_scale(double s0, double s2, double2 t, double2 p2, double2 m2,
+                                           double2* __restrict__ q, int64_t nalm) {
+    q[0] = make_double2(s0 * t.x, s0 * t.y);
+    q[nalm] = make_double2(s2 * p2.x, s2 * p2.y);
+    q[2 * nalm] = make_double2(s2 * m2.x, s2 * m2.y);
+}
+
 // fixed-order sum of (a, b) over the 256 threads of a combine block into
 // cpart[rhs][block][2]; every thread of the block must call it once
 __device__ void cauchy_block_sum(double a, double b, double* __restrict__ cpart, int nrhs) {
@@ -550,11 +559,15 @@ __global__ __launch_bounds__(256) void cauchy_reduce_kernel(const double* __rest
 
 // cpart (nullable): per-block sums of w |u_new - u_old|^2 and w |u_new|^2
 // over T, E, B (w = 2 for m > 0), the Cauchy ratio's terms; the old value
-// is what alm holds on entry
+// is what alm holds on entry.  scale (nullable, [nalm][2]): the batched
+// kernels' recursion scales S (spin 0, spin 2); the partial sums are
+// multiplied by S, and so is the spin-basis copy (the batched synthesis
+// contracts the scaled functions with it).
 __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, int nchunks, int nrhs,
                                                       const double2* __restrict__ partial,
                                                       const double* __restrict__ filt, double2* __restrict__ alm,
-                                                      double2* __restrict__ spin, double* __restrict__ cpart) {
+                                                      double2* __restrict__ spin, double* __restrict__ cpart,
+                                                      const double* __restrict__ scale) {
     const int m = blockIdx.y;
     const int rhs = blockIdx.z;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
@@ -571,6 +584,14 @@ __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, in
                 s.y += v.y;
             }
             a[f] = s;
+        }
+        double s0 = 1.0, s2 = 1.0;
+        if (scale) {
+            s0 = scale[2 * idx];
+            s2 = scale[2 * idx + 1];
+            a[0] = make_double2(s0 * a[0].x, s0 * a[0].y);
+            a[1] = make_double2(s2 * a[1].x, s2 * a[1].y);
+            a[2] = make_double2(s2 * a[2].x, s2 * a[2].y);
         }
         // E = -((2)a + (-2)a)/2,  B = i((2)a - (-2)a)/2
         double2 E = make_double2(-0.5 * (a[1].x + a[2].x), -0.5 * (a[1].y + a[2].y));
@@ -604,18 +625,17 @@ __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, in
             double2* q = spin + ((int64_t)rhs * 3) * nalm + idx;
             double2 p2, m2;
             eb_to_spin(E, B, p2, m2);
-            q[0] = T;
-            q[nalm] = p2;
-            q[2 * nalm] = m2;
+            spin_scale(s0, s2, T, p2, m2, q, nalm);
         }
     }
     // cpart is uniform over the grid, so the whole block takes this branch
     if (cpart) cauchy_block_sum(dd, nn, cpart, nrhs);
 }
 
-// (T, E, B) -> (T, (2)a, (-2)a)
+// (T, E, B) -> (T, (2)a, (-2)a), times the recursion scales if scale is
+// given (the same arithmetic as the combine kernel's spin-basis copy)
 __global__ void to_spin_kernel(int64_t nalm, int64_t total, const double2* __restrict__ alm,
-                               double2* __restrict__ spin) {
+                               double2* __restrict__ spin, const double* __restrict__ scale) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rhs = i / nalm, idx = i % nalm;
@@ -623,9 +643,8 @@ __global__ void to_spin_kernel(int64_t nalm, int64_t total, const double2* __res
         double2* q = spin + rhs * 3 * nalm + idx;
         double2 p2, m2;
         eb_to_spin(a[nalm], a[2 * nalm], p2, m2);
-        q[0] = a[0];
-        q[nalm] = p2;
-        q[2 * nalm] = m2;
+        const double s0 = scale ? scale[2 * idx] : 1.0, s2 = scale ? scale[2 * idx + 1] : 1.0;
+        spin_scale(s0, s2, a[0], p2, m2, q, nalm);
     }
 }
 
@@ -676,11 +695,11 @@ void set_analysis_tiling(dm_plan* p, int R) {
 }
 
 hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
-                          double* alm, double* spin, double* cpart, hipStream_t s) {
+                          double* alm, double* spin, double* cpart, const double* scale, hipStream_t s) {
     dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
     hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
                        reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
-                       reinterpret_cast<double2*>(spin), cpart);
+                       reinterpret_cast<double2*>(spin), cpart, scale);
     return hipGetLastError();
 }
 
@@ -691,12 +710,13 @@ hipError_t launch_cauchy_reduce(dm_plan* p, int nrhs, const double* cpart, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, hipStream_t s) {
+hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, const double* scale,
+                          hipStream_t s) {
     const int64_t total = (int64_t)nrhs * p->nalm;
     int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(to_spin_kernel, dim3((int)g), dim3(256), 0, s, p->nalm, total,
-                       reinterpret_cast<const double2*>(alm), reinterpret_cast<double2*>(spin));
+                       reinterpret_cast<const double2*>(alm), reinterpret_cast<double2*>(spin), scale);
     return hipGetLastError();
 }
 

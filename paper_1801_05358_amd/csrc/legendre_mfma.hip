@@ -122,31 +122,39 @@ struct BatchArgs {
     int mchunk;                     // consecutive m per XCD chunk (0: plain order)
     int64_t nalm;
     const double* __restrict__ pair_x;
-    const double* __restrict__ coef;
+    const double* __restrict__ coef;    // scaled recursions, [nalm][kCoefSStride]
+    const double* __restrict__ scale;   // their scales S, [nalm][2]
     const int* __restrict__ lstart;
     const double* __restrict__ seed;
     int64_t sstride;
 };
 
-// FP64 recursion of one ring pair: lam, p, q at (l-1, l).
+// FP64 recursion of one ring pair: lam, p, q at (l-1, l), and the pair's
+// seeds, loaded once at the start so that taking them needs no memory wait
+// (a load at activation time waits, through the in-order vector memory
+// counter, for every load issued before it: 2 % of both kernels' time)
 struct Rec {
     double x, l0, l1, w0, w1, q0, q1;
+    double sd[6];
     int ls, pr;
 };
 
-// recursion coefficients of one degree: spin 0 (A, B), spin 2 (alpha,
-// alpha beta, gamma)
+// coefficients of one degree of the scaled recursions: spin 0 (A0'), spin 2
+// (alpha', (alpha beta)'); the degree l-2 term has coefficient 1.  The
+// functions carried are mu = lam / S (S per (l, m), spin 0 and spin 2): the
+// contraction inputs and outputs are multiplied by S outside these kernels.
 struct Coef {
-    double a, b, al, ab, ga;
+    double a, al, ab;
 };
 
-__device__ __forceinline__ Coef coef_at(const double* __restrict__ c) { return Coef{c[0], c[1], c[2], c[3], c[4]}; }
+__device__ __forceinline__ Coef coef_at(const double* __restrict__ c) { return Coef{c[0], c[1], c[2]}; }
 
 __device__ __forceinline__ void rec_advance(const Coef& c, Rec& s) {
-    const double ax = c.a * s.x, bx = c.al * s.x;
-    const double nl = ax * s.l1 - c.b * s.l0;
-    const double nw = (bx + c.ab) * s.w1 - c.ga * s.w0;
-    const double nq = (bx - c.ab) * s.q1 - c.ga * s.q0;
+    const double ax = c.a * s.x;
+    const double cw = c.al * s.x + c.ab, cq = c.al * s.x - c.ab;
+    const double nl = ax * s.l1 - s.l0;
+    const double nw = cw * s.w1 - s.w0;
+    const double nq = cq * s.q1 - s.q0;
     s.l0 = s.l1; s.l1 = nl;
     s.w0 = s.w1; s.w1 = nw;
     s.q0 = s.q1; s.q1 = nq;
@@ -157,56 +165,73 @@ __device__ __forceinline__ void rec_advance(const double* __restrict__ c, Rec& s
 // The recursion coefficients reach the steady loops through LDS rather than
 // scalar loads: scalar and LDS loads share one wait counter and scalar loads
 // return out of order, so every wait for an LDS operand would also wait for
-// the coefficient loads.  A group of G degrees (5 coefficients each) is
+// the coefficient loads.  A group of G degrees (3 coefficients each) is
 // loaded one round ahead by lane t < 5G (one double each, vector loads),
 // stored to LDS in the following round and read as broadcasts in the round
 // after.  Every lane loads and stores (lanes >= 5G repeat the last value
 // into their own slot), so the loop body has no branch and the wait for the
 // load stays precise; degrees past lmax are clamped to lmax (a group past
 // lmax is loaded but never used).
-constexpr int kCoefN = 5;
+constexpr int kCoefN = 3;
 
 __device__ __forceinline__ double coef_fetch(const double* __restrict__ cf, int l0, int lmax, int t, int G) {
     const int tc = min(t, G * kCoefN - 1);
     const int d = tc / kCoefN, i = tc - d * kCoefN;
-    return cf[(int64_t)min(l0 + d, lmax) * kCoefStride + i];
+    return cf[(int64_t)min(l0 + d, lmax) * kCoefSStride + i];
 }
 
-__device__ __forceinline__ Coef coef_lds(const double* c) { return Coef{c[0], c[1], c[2], c[3], c[4]}; }
+__device__ __forceinline__ Coef coef_lds(const double* c) { return Coef{c[0], c[1], c[2]}; }
 
 __device__ __forceinline__ void rec_activate(const BatchArgs& A, int m, int l, Rec& s) {
-    const int64_t o = (int64_t)m * A.npairs + s.pr;
     if (l == s.ls) {
-        s.l0 = A.seed[0 * A.sstride + o];
-        s.l1 = A.seed[1 * A.sstride + o];
+        s.l0 = s.sd[0];
+        s.l1 = s.sd[1];
         if (m >= 2) {
-            s.w0 = A.seed[2 * A.sstride + o];
-            s.w1 = A.seed[3 * A.sstride + o];
-            s.q0 = A.seed[4 * A.sstride + o];
-            s.q1 = A.seed[5 * A.sstride + o];
+            s.w0 = s.sd[2];
+            s.w1 = s.sd[3];
+            s.q0 = s.sd[4];
+            s.q1 = s.sd[5];
         }
     }
     if (m < 2 && l == 2 && s.ls <= A.lmax) {
-        s.w0 = A.seed[2 * A.sstride + o];
-        s.w1 = A.seed[3 * A.sstride + o];
-        s.q0 = A.seed[4 * A.sstride + o];
-        s.q1 = A.seed[5 * A.sstride + o];
+        s.w0 = s.sd[2];
+        s.w1 = s.sd[3];
+        s.q0 = s.sd[4];
+        s.q1 = s.sd[5];
     }
 }
 
+// call before the kernel's other global loads: the seeds then arrive first,
+// and waiting for them does not wait for the loads issued after them.  The
+// seeds (lam at the degrees before and at the start) become mu = lam / S.
 __device__ __forceinline__ void rec_init(Rec& s, const BatchArgs& A, int m, int p) {
     const bool ok = p < A.npairs;
     s.pr = ok ? p : 0;
     s.x = ok ? A.pair_x[p] : 0.0;
     s.ls = ok ? A.lstart[(int64_t)m * A.npairs + p] : A.lmax + 1;
     s.l0 = s.l1 = s.w0 = s.w1 = s.q0 = s.q1 = 0.0;
+    const int64_t o = (int64_t)m * A.npairs + s.pr;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s.sd[i] = A.seed[i * A.sstride + o];
+    // degrees of the seeds, clamped into [m, lmax] (a seed below m is 0; an
+    // inactive lane's seeds are never taken)
+    const double* sc = A.scale + mbase(m, A.lmax) * 2;
+    auto at = [&](int l) { return (int64_t)min(max(l, m), A.lmax) * 2; };
+    const int l2 = m < 2 ? 2 : s.ls;             // spin 2 of m < 2 starts at l = 2
+    s.sd[0] /= sc[at(s.ls - 1)];
+    s.sd[1] /= sc[at(s.ls)];
+    const double s2a = sc[at(l2 - 1) + 1], s2b = sc[at(l2) + 1];
+    s.sd[2] /= s2a;
+    s.sd[3] /= s2b;
+    s.sd[4] /= s2a;
+    s.sd[5] /= s2b;
 }
 
 // one recursion step to degree l (zero beyond lmax)
 __device__ __forceinline__ void rec_step(const BatchArgs& A, const double* __restrict__ cf, int m, int l, int lo,
                                          int hi, Rec& s, double& lam, double& pp, double& qq) {
     if (l <= A.lmax) {
-        if (l > lo) rec_advance(cf + (int64_t)l * kCoefStride, s);
+        if (l > lo) rec_advance(cf + (int64_t)l * kCoefSStride, s);
         if (l <= hi) rec_activate(A, m, l, s);
         lam = s.l1;
         pp = s.w1;
@@ -220,7 +245,7 @@ __device__ __forceinline__ void rec_step(const BatchArgs& A, const double* __res
 // past its start degree, degree <= lmax): no branch, so the compiler can
 // interleave it with the matrix instructions of the current round
 __device__ __forceinline__ void rec_next(const double* __restrict__ cf, int l, Rec& s) {
-    rec_advance(cf + (int64_t)l * kCoefStride, s);
+    rec_advance(cf + (int64_t)l * kCoefSStride, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,7 +318,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     const int rb = blockIdx.y * 8;
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
-    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const double* __restrict__ cf = A.coef + base * kCoefSStride;
     SynTile<T, PW>* tile = reinterpret_cast<SynTile<T, PW>*>(&lds[wv][0]);
     // the ring pair this lane recurses; with PW < 64 the upper lanes repeat
     // the lower ones and store the same values to the same addresses
@@ -477,7 +502,7 @@ constexpr int kRedF = 16 * kRedCol;
 // recursion of an activation round: every lane advances (lanes before
 // their start degree hold zeros), lanes whose start degree is l take seeds
 __device__ __forceinline__ void rec_act(const BatchArgs& A, const double* __restrict__ cf, int m, int l, Rec& s) {
-    rec_advance(cf + (int64_t)l * kCoefStride, s);
+    rec_advance(cf + (int64_t)l * kCoefSStride, s);
     rec_activate(A, m, l, s);
 }
 
@@ -489,7 +514,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     constexpr int RL = ana_rl<T>();
     __shared__ T tile[W][ana_tile<T>()];
     __shared__ T red[2][W][3 * kRedF];
-    __shared__ double cofb[2][128];                     // recursion coefficients of 16 degrees
+    __shared__ double cofb[2][64];                      // recursion coefficients of 16 degrees
     __shared__ int s_lo[W], s_hi[W];
     const BlockPos bp = block_pos(A.nx, A.mchunk);
     const int m = bp.m;
@@ -499,7 +524,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     const int rb = blockIdx.y * 8;
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
-    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const double* __restrict__ cf = A.coef + base * kCoefSStride;
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
 
     Rec s;
@@ -582,11 +607,8 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     };
     // coefficient pipeline (wave 0): cofb[cq] holds the degrees the current
     // round's recursion needs, creg the 16 degrees after them
-    auto coef_group = [&](int l, int slot) {
-        cofb[slot][lane] = coef_fetch(cf, l, lmax, lane, 16);
-        cofb[slot][lane + 64] = coef_fetch(cf, l, lmax, lane + 64, 16);
-    };
-    double creg0 = 0.0, creg1 = 0.0;
+    auto coef_group = [&](int l, int slot) { cofb[slot][lane] = coef_fetch(cf, l, lmax, lane, 16); };
+    double creg0 = 0.0;
 
     // A operand of this lane: degree row, pair 4 (st % KH) + k; the mirror
     // half reads (lam, q, p)
@@ -629,7 +651,6 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     if (wv == 0) {
         coef_group(lo + 16, 0);
         creg0 = coef_fetch(cf, lo + 32, lmax, lane, 16);
-        creg1 = coef_fetch(cf, lo + 32, lmax, lane + 64, 16);
     }
     __syncthreads();
     int q = 0, l0 = lo;
@@ -653,9 +674,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
             // publish the next round's coefficients (visible after this
             // round's barrier), fetch the ones after them
             cofb[q ^ 1][lane] = creg0;
-            cofb[q ^ 1][lane + 64] = creg1;
             creg0 = coef_fetch(cf, l0 + 48, lmax, lane, 16);
-            creg1 = coef_fetch(cf, l0 + 48, lmax, lane + 64, 16);
         }
         // the products have read the tile (LDS operations of a wave
         // complete in order): the next round's recursion overwrites it
@@ -684,7 +703,8 @@ BatchArgs batch_args(dm_plan* p, int nrhs) {
     a.nrhs = nrhs;
     a.nalm = p->nalm;
     a.pair_x = p->d_pair_x;
-    a.coef = p->d_coef;
+    a.coef = p->d_coef_s;
+    a.scale = p->d_scale;
     a.lstart = p->d_lstart;
     a.seed = p->d_seed;
     a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
