@@ -613,7 +613,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         p->npairs = (int)p->rings.pair_n.size();
         p->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
         REQUIRE(build_fft_tables(p->rings, p->mmax, p->fft, e), DM_EINVAL, e);
-        p->fft_lds_bytes = (size_t)(p->fft.Mmax + p->fft.Mmax / 8) * 16;     // padded layout (ringfft.hip)
+        p->fft_lds_bytes = (size_t)(p->fft.Mmax + p->fft.Mmax / 8 + 8) * 16;     // padded layout (ringfft.hip)
         REQUIRE(p->fft_lds_bytes <= 160 * 1024, DM_EUNSUPPORTED,
                 "ring length needs an FFT of " + std::to_string(p->fft.Mmax) +
                     " points, beyond the LDS of one workgroup in double precision");

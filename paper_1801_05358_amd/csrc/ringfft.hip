@@ -56,10 +56,14 @@ struct RingArgs {
     const C2<R>* __restrict__ tw;
 };
 
-// LDS layout of a transform buffer: element i at i + i/8, so that the
-// stride-8 and stride-64 element groups of the first radix-8 passes fall in
-// distinct banks (one pad element per 8)
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+// LDS layout of a transform buffer of size M = 2^logM: element i at
+// i + i/8 + i/(M/8), with sh = logM - 3.  Eight consecutive lanes then hit
+// eight distinct 16-byte bank groups both for the strided groups of the
+// radix-8 passes (the i/8 term) and for bit-reversed positions, which differ
+// by multiples of M/8 (the last term): the pixel loop and the Bluestein
+// unfold address the buffer that way.
+__device__ __forceinline__ int pad_shift(int logM) { return logM > 6 ? logM - 3 : 3; }
+__device__ __forceinline__ int pidx(int i, int sh) { return i + (i >> 3) + (i >> sh); }
 
 template <typename C>
 __device__ __forceinline__ C cmul(C a, C b) {
@@ -109,8 +113,8 @@ __device__ __forceinline__ C2<R> root_mul(C2<R> w, int r, int t, bool inv) {
 }
 
 template <typename R, int G, bool DIT>
-__device__ __forceinline__ void fft_pass(C2<R>* buf, int M, int s, int logMmax, const C2<R>* __restrict__ tw,
-                                         bool inv) {
+__device__ __forceinline__ void fft_pass(C2<R>* buf, int M, int sh, int s, int logMmax,
+                                         const C2<R>* __restrict__ tw, bool inv) {
     constexpr int NG = 1 << G;
     const int h = 1 << s;
     const int ngroups = M >> G;
@@ -119,7 +123,7 @@ __device__ __forceinline__ void fft_pass(C2<R>* buf, int M, int s, int logMmax, 
         const int base = ((q >> s) << (s + G)) + j;
         C2<R> x[NG];
 #pragma unroll
-        for (int c = 0; c < NG; ++c) x[c] = buf[pidx(base + c * h)];
+        for (int c = 0; c < NG; ++c) x[c] = buf[pidx(base + c * h, sh)];
         C2<R> wb[G];
 #pragma unroll
         for (int t = 0; t < G; ++t) {
@@ -146,7 +150,7 @@ __device__ __forceinline__ void fft_pass(C2<R>* buf, int M, int s, int logMmax, 
             }
         }
 #pragma unroll
-        for (int c = 0; c < NG; ++c) buf[pidx(base + c * h)] = x[c];
+        for (int c = 0; c < NG; ++c) buf[pidx(base + c * h, sh)] = x[c];
     }
     __syncthreads();
 }
@@ -154,19 +158,21 @@ __device__ __forceinline__ void fft_pass(C2<R>* buf, int M, int s, int logMmax, 
 // decimation in time: bit-reversed input, natural output
 template <typename R>
 __device__ void fft_dit(C2<R>* buf, int M, int logM, int logMmax, const C2<R>* __restrict__ tw, bool inv) {
+    const int sh = pad_shift(logM);
     int s = 0;
-    for (; s + 3 <= logM; s += 3) fft_pass<R, 3, true>(buf, M, s, logMmax, tw, inv);
-    if (logM - s == 2) fft_pass<R, 2, true>(buf, M, s, logMmax, tw, inv);
-    else if (logM - s == 1) fft_pass<R, 1, true>(buf, M, s, logMmax, tw, inv);
+    for (; s + 3 <= logM; s += 3) fft_pass<R, 3, true>(buf, M, sh, s, logMmax, tw, inv);
+    if (logM - s == 2) fft_pass<R, 2, true>(buf, M, sh, s, logMmax, tw, inv);
+    else if (logM - s == 1) fft_pass<R, 1, true>(buf, M, sh, s, logMmax, tw, inv);
 }
 
 // decimation in frequency: natural input, bit-reversed output
 template <typename R>
 __device__ void fft_dif(C2<R>* buf, int M, int logM, int logMmax, const C2<R>* __restrict__ tw, bool inv) {
+    const int sh = pad_shift(logM);
     int top = logM;
-    for (; top >= 3; top -= 3) fft_pass<R, 3, false>(buf, M, top - 3, logMmax, tw, inv);
-    if (top == 2) fft_pass<R, 2, false>(buf, M, 0, logMmax, tw, inv);
-    else if (top == 1) fft_pass<R, 1, false>(buf, M, 0, logMmax, tw, inv);
+    for (; top >= 3; top -= 3) fft_pass<R, 3, false>(buf, M, sh, top - 3, logMmax, tw, inv);
+    if (top == 2) fft_pass<R, 2, false>(buf, M, sh, 0, logMmax, tw, inv);
+    else if (top == 1) fft_pass<R, 1, false>(buf, M, sh, 0, logMmax, tw, inv);
 }
 
 // Forward DFT core.  On entry buf[brev(j)] holds a_j (times chirp_j for
@@ -179,7 +185,8 @@ __device__ void dft_core(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A) {
     } else {
         fft_dit<R>(buf, L.M, L.logM, A.logMmax, A.tw, false);
         const C2<R>* bh = A.bhat + L.bhat_off;
-        for (int q = threadIdx.x; q < L.M; q += blockDim.x) buf[pidx(q)] = cmul(buf[pidx(q)], bh[q]);
+        const int sh = pad_shift(L.logM);
+        for (int q = threadIdx.x; q < L.M; q += blockDim.x) buf[pidx(q, sh)] = cmul(buf[pidx(q, sh)], bh[q]);
         __syncthreads();
         fft_dif<R>(buf, L.M, L.logM, A.logMmax, A.tw, true);
     }
@@ -214,7 +221,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
     if (p >= A.npairs) return;
     const RingPairDev P_ = A.pairs[p];
     const FftLenDev L = A.lens[P_.len_idx];
-    const int n = P_.nphi, M = L.M, logM = L.logM;
+    const int n = P_.nphi, M = L.M, logM = L.logM, sh = pad_shift(logM);
     const int nt = blockDim.x, tid = threadIdx.x;
     const int mmax = A.mmax;
     const bool synth = (MODE == RING_SYNTH || MODE == RING_ITERATE);
@@ -240,14 +247,27 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
         CP* ph = phase + (((int64_t)rhs * 3 + f) * A.npairs + p) * (mmax + 1) * 2;
         const int64_t moff = ((int64_t)rhs * 3 + f) * A.npix;
         if (synth) {
-            // fold into n bins, place conj(C_N + i C_S) for the inverse transform
-            for (int k = tid; k < M; k += nt) {
+            // fold into n bins, place conj(C_N + i C_S) for the inverse
+            // transform.  Lanes take consecutive logical indices j (coalesced
+            // ring-data reads; the slot is brev(j) for Bluestein lengths).
+            // e^{i mstart phi0} = e^{i j phi0} e^{-i w n phi0} with
+            // mstart = j - w n: the first factor advances by e^{i nt phi0}
+            // from one j of a lane to the next, and the second is (-1)^w on
+            // rings with n phi0 = pi (HEALPix) and 1 for phi0 = 0.
+            const bool half_turn = P_.phi0_den == n;
+            CR rotj = phase_rot<R>(tid, P_.phi0_den);
+            const CR rstep = phase_rot<R>(nt, P_.phi0_den);
+            for (int j = tid; j < M; j += nt, rotj = cmul(rotj, rstep)) {
                 CR v = zero;
-                const int j = L.bluestein ? (int)brev(k, logM) : k;   // logical index of slot k
+                const int k = L.bluestein ? (int)brev(j, logM) : j;   // slot of logical index j
                 if (j < n) {
                     CR cn = zero, cs = zero;
-                    const int mstart = j - n * ((j + mmax) / n);
-                    CR rot = phase_rot<R>(mstart, P_.phi0_den);
+                    const int w = (j + mmax) / n;
+                    const int mstart = j - n * w;
+                    CR rot;
+                    if (P_.phi0_den == 0) rot = mk<R>(1, 0);
+                    else if (half_turn) rot = (w & 1) ? mk<R>(-rotj.x, -rotj.y) : rotj;
+                    else rot = phase_rot<R>(mstart, P_.phi0_den);
                     for (int m = mstart; m <= mmax; m += n) {
                         const int a = m < 0 ? -m : m;
                         const CP fnd = ph[2 * a], fsd = ph[2 * a + 1];
@@ -262,14 +282,14 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                     v = mk<R>(cn.x - cs.y, -(cn.y + cs.x));
                     if (L.bluestein) v = cmul(v, chirp[j]);
                 }
-                buf[pidx(k)] = v;
+                buf[pidx(k, sh)] = v;
             }
             __syncthreads();
             idft_core<R>(buf, L, A);
             // now x_j (packed N + i S) = conj(buf[brev(j)] * chirp_j)
             for (int j = tid; j < n; j += nt) {
                 const int q = (int)brev(j, logM);
-                CR y = buf[pidx(q)];
+                CR y = buf[pidx(q, sh)];
                 if (L.bluestein) y = cmul(y, chirp[j]);
                 const double xn = (double)y.x, xs = -(double)y.y;
                 if (MODE == RING_SYNTH) {
@@ -289,11 +309,11 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                     }
                     CR a = mk<R>((R)tn, (R)ts);
                     if (L.bluestein) a = cmul(a, chirp[j]);
-                    buf[pidx(q)] = a;
+                    buf[pidx(q, sh)] = a;
                 }
             }
             if (MODE == RING_ITERATE && L.bluestein) {
-                for (int j = n + tid; j < M; j += nt) buf[pidx((int)brev(j, logM))] = zero;
+                for (int j = n + tid; j < M; j += nt) buf[pidx((int)brev(j, logM), sh)] = zero;
             }
             __syncthreads();
         }
@@ -306,7 +326,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                     a.y = P_.has_s ? (R)map_in[moff + P_.off_s + j] : R(0);
                     if (L.bluestein) a = cmul(a, chirp[j]);
                 }
-                buf[pidx(q)] = a;
+                buf[pidx(q, sh)] = a;
             }
             __syncthreads();
         }
@@ -318,7 +338,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                 const int k2 = (n - k) % n;
                 const int q1 = L.bluestein ? (int)brev(k, logM) : k;
                 const int q2 = L.bluestein ? (int)brev(k2, logM) : k2;
-                CR z1 = buf[pidx(q1)], z2 = buf[pidx(q2)];
+                CR z1 = buf[pidx(q1, sh)], z2 = buf[pidx(q2, sh)];
                 if (L.bluestein) { z1 = cmul(z1, chirp[k]); z2 = cmul(z2, chirp[k2]); }
                 const CR xn = mk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
                 const CR xs = mk<R>(R(0.5) * (z1.y + z2.y), R(-0.5) * (z1.x - z2.x));
@@ -362,7 +382,7 @@ void launch_ring_t(dm_plan* p, int mode, int nrhs, const double* map_in, double*
     Ar.nrhs = nrhs;
     dim3 grid((unsigned)(((p->npairs + 7) / 8) * 8 * nrhs));
     dim3 block(p->fft_threads);
-    const size_t lds = (size_t)(p->fft.Mmax + p->fft.Mmax / 8) * sizeof(C2<R>);
+    const size_t lds = (size_t)(p->fft.Mmax + p->fft.Mmax / 8 + 8) * sizeof(C2<R>);
     switch (mode) {
         case RING_ANALYSIS:
             hipLaunchKernelGGL((ring_kernel<RING_ANALYSIS, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
