@@ -113,6 +113,12 @@ void collect_events(dm_plan* p) {
 // --------------------------------------------------------------------------
 // transform building blocks
 // --------------------------------------------------------------------------
+// integer setting from the environment (tuning and test knobs)
+int env_int(const char* k, int dflt) {
+    const char* v = std::getenv(k);
+    return v ? std::atoi(v) : dflt;
+}
+
 bool use_mfma(dm_plan* p, int nrhs);
 
 // ring Fourier data: FP32 storage for the mixed matrix-core transforms
@@ -519,6 +525,7 @@ void free_plan(dm_plan* p) {
         (void)hipEventDestroy(p->ev.stop[i]);
     }
     dfree(p->d_pair_x); dfree(p->d_pair_w); dfree(p->d_pair_one); dfree(p->d_pairs); dfree(p->d_fftlen);
+    dfree(p->d_plist_whole); dfree(p->d_plist_split);
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
     dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_coef_s); dfree(p->d_scale); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
@@ -612,10 +619,22 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         p->nrings = (int)p->rings.z.size();
         p->npairs = (int)p->rings.pair_n.size();
         p->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
-        REQUIRE(build_fft_tables(p->rings, p->mmax, p->fft, e), DM_EINVAL, e);
-        p->fft_lds_bytes = (size_t)(p->fft.Mmax + p->fft.Mmax / 8 + 8) * 16;     // padded layout (ringfft.hip)
+        // the largest padded FP64 transform buffer within one workgroup's
+        // 160 KB of LDS (DMWF_FFT_MAX_ELEMS lowers it, to exercise the split
+        // transform on small grids)
+        const int max_elems = std::max(8, std::min(8192, env_int("DMWF_FFT_MAX_ELEMS", 8192)));
+        REQUIRE(build_fft_tables(p->rings, p->mmax, max_elems, p->fft, e), DM_EINVAL, e);
+        for (size_t i = 0; i < p->fft.n.size(); ++i) {
+            if (!p->fft.split[i]) continue;
+            const int i4 = p->fft.n[i] / 4;
+            REQUIRE(i4 <= 4 * p->fft_threads, DM_EUNSUPPORTED,
+                    "ring length " + std::to_string(p->fft.n[i]) + " is too long for the split transform");
+            if (i4 > 2 * p->fft_threads) p->split_k = 4;
+        }
+        const int lds_max = std::max(p->fft.lds_elems, p->fft.lds_split);
+        p->fft_lds_bytes = (size_t)(lds_max + lds_max / 8 + 8) * 16;   // padded layout (ringfft.hip)
         REQUIRE(p->fft_lds_bytes <= 160 * 1024, DM_EUNSUPPORTED,
-                "ring length needs an FFT of " + std::to_string(p->fft.Mmax) +
+                "ring length needs a transform buffer of " + std::to_string(lds_max) +
                     " points, beyond the LDS of one workgroup in double precision");
         HIPCHK(hipStreamCreate(&p->stream));
 
@@ -643,8 +662,22 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
             fl[i].M = p->fft.M[i];
             fl[i].logM = p->fft.logM[i];
             fl[i].bluestein = p->fft.chirp_off[i] >= 0;
+            fl[i].split = p->fft.split[i];
             fl[i].chirp_off = std::max<int64_t>(p->fft.chirp_off[i], 0);
             fl[i].bhat_off = std::max<int64_t>(p->fft.bhat_off[i], 0);
+        }
+        {
+            std::vector<int> whole, split;
+            for (int q = 0; q < p->npairs; ++q) (p->fft.split[pd[q].len_idx] ? split : whole).push_back(q);
+            p->n_whole = (int)whole.size();
+            p->n_split = (int)split.size();
+            if (p->n_split) {
+                dalloc(p, p->d_plist_whole, std::max<size_t>(whole.size(), 1));
+                dalloc(p, p->d_plist_split, split.size());
+                if (!whole.empty()) upload(p, p->d_plist_whole, whole.data(), whole.size());
+                upload(p, p->d_plist_split, split.data(), split.size());
+                HIPCHK(hipStreamSynchronize(p->stream));
+            }
         }
         dalloc(p, p->d_pair_x, p->npairs);
         dalloc(p, p->d_pair_w, p->npairs);
@@ -713,10 +746,6 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         // tiling of the Legendre kernels (ring pairs per lane R); the
         // DMWF_ANA_R / DMWF_SYN_R / DMWF_SYN_THREADS / DMWF_*_MCHUNK
         // environment variables override the defaults for tuning sweeps
-        auto env_int = [](const char* k, int dflt) {
-            const char* v = std::getenv(k);
-            return v ? std::atoi(v) : dflt;
-        };
         int ar = env_int("DMWF_ANA_R", p->npairs >= 2048 ? 2 : 1);
         if (ar != 1 && ar != 2 && ar != 4) ar = 2;
         set_analysis_tiling(p, ar);

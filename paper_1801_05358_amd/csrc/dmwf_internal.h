@@ -38,11 +38,15 @@ struct RingTables {
 struct FftTables {
     // distinct ring lengths
     std::vector<int> n;           // length
-    std::vector<int> M;           // transform size (n if n is a power of two, else Bluestein size)
+    std::vector<int> split;       // 1: n = 4 i transformed as four length-i DFTs
+    std::vector<int> M;           // transform size (n if n is a power of two, else the Bluestein
+                                  // size of n, or of n/4 when split)
     std::vector<int> logM;
     std::vector<int64_t> chirp_off;   // offset into chirp (complex) or -1
     std::vector<int64_t> bhat_off;    // offset into bhat (complex) or -1
-    int Mmax = 1;
+    int Mmax = 1;                 // largest power-of-two transform (the twiddle table's size)
+    int lds_elems = 1;            // largest transform buffer of the unsplit lengths (complex elements)
+    int lds_split = 1;            // the same for the split lengths: max(n, M)
     std::vector<double> chirp;    // interleaved complex, exp(-i pi j^2 / n)
     std::vector<double> bhat;     // interleaved complex, FFT_M(b) / M
     std::vector<double> tw;       // interleaved complex, exp(-2 pi i k / Mmax), k < Mmax/2
@@ -58,7 +62,7 @@ struct RingPairDev {
 };
 
 struct FftLenDev {
-    int n, M, logM, bluestein;
+    int n, M, logM, bluestein, split;
     int64_t chirp_off, bhat_off;
 };
 
@@ -110,6 +114,12 @@ struct dm_plan {
     int syn_threads = 128, syn_R = 1;
     int syn_mchunk = 4, ana_mchunk = 4;               // batched kernels: consecutive m per XCD chunk
     int fft_threads = 512;
+    // ring pairs of the unsplit and the split lengths (the split launch runs
+    // only when some length is split)
+    int n_whole = 0, n_split = 0;
+    int split_k = 2;                   // kappa values per lane of the split launch (2 or 4)
+    int* d_plist_whole = nullptr;
+    int* d_plist_split = nullptr;
     size_t fft_lds_bytes = 0;
 
     // noise
@@ -198,7 +208,8 @@ bool build_rings(const dm_grid& g, RingTables& rt, int64_t& npix, std::string& e
 void build_scaled_coefficients(int lmax, std::vector<double>& coef_s, std::vector<double>& scale);
 void build_coefficients(int lmax, std::vector<double>& coef, std::vector<double>& lp0,
                         std::vector<double>& lp2);
-bool build_fft_tables(const RingTables& rt, int mmax, FftTables& ft, std::string& err);
+// lengths whose Bluestein buffer would exceed max_elems are split
+bool build_fft_tables(const RingTables& rt, int mmax, int max_elems, FftTables& ft, std::string& err);
 void build_filter(const std::vector<double>& cl, int lmax, double mu, double tau, std::vector<double>& F);
 void build_matrix_function(const std::vector<double>& cl, int lmax, int which, std::vector<double>& F);
 

@@ -13,8 +13,10 @@
 //               back into the two rings by Hermitian symmetry.
 // Lengths that are powers of two use a radix-2 FFT in LDS; other lengths
 // (most HEALPix polar rings, 4i) use Bluestein's chirp-z convolution with a
-// power-of-two FFT of size M >= 2n - 1, also in LDS.  Inverse transforms
-// are conj(DFT(conj(.))).
+// power-of-two FFT of size M >= 2n - 1, also in LDS.  Where that M would be
+// the largest buffer of the plan, a length n = 4i is split by decimation
+// (four length-i Bluestein transforms and a radix-4 step), which needs
+// max(n, M_i) elements instead.  Inverse transforms are conj(DFT(conj(.))).
 #include "dmwf_internal.h"
 
 namespace dmwf {
@@ -48,6 +50,8 @@ __device__ __forceinline__ C2<R> mk(R x, R y) {
 template <typename R>
 struct RingArgs {
     int npairs, mmax, logMmax, nrhs;
+    const int* __restrict__ plist;   // the launch's ring pairs (null: all, in order)
+    int nlist;
     int64_t npix;
     const RingPairDev* __restrict__ pairs;
     const FftLenDev* __restrict__ lens;
@@ -204,7 +208,32 @@ __device__ void idft_core(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A) 
     }
 }
 
-template <int MODE, typename R, typename P>
+
+// out[r] = sum_q (-i)^{r q} v_q (a length-4 DFT)
+template <typename R>
+__device__ __forceinline__ void dft4(C2<R> v0, C2<R> v1, C2<R> v2, C2<R> v3, C2<R> (&out)[4]) {
+    const C2<R> a = mk<R>(v0.x + v2.x, v0.y + v2.y), b = mk<R>(v0.x - v2.x, v0.y - v2.y);
+    const C2<R> c = mk<R>(v1.x + v3.x, v1.y + v3.y), d = mk<R>(v1.x - v3.x, v1.y - v3.y);
+    out[0] = mk<R>(a.x + c.x, a.y + c.y);
+    out[2] = mk<R>(a.x - c.x, a.y - c.y);
+    out[1] = mk<R>(b.x + d.y, b.y - d.x);   // b - i d
+    out[3] = mk<R>(b.x - d.y, b.y + d.x);   // b + i d
+}
+
+// exp(-2 pi i e / n) for 0 <= e < n
+template <typename R>
+__device__ __forceinline__ C2<R> unit_root(int e, int n) {
+    R sn, cs;
+    if constexpr (sizeof(R) == 8) sincospi(2.0 * (double)e / (double)n, &sn, &cs);
+    else sincospif(2.0f * (float)e / (float)n, &sn, &cs);
+    return mk<R>(cs, -sn);
+}
+
+// SPLITK > 0: the launch over the split rings (n = 4 i, see split_ring
+// below), each lane holding SPLITK values of kappa (i <= SPLITK blockDim.x,
+// checked when the plan is made); the other rings run in a launch of their
+// own, so that neither carries the other's registers or buffer size.
+template <int MODE, int SPLITK, typename R, typename P>
 __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* __restrict__ map_in,
                                                    double* __restrict__ map_out, const double* __restrict__ Kp,
                                                    const double* __restrict__ bp, C2<P>* __restrict__ phase) {
@@ -217,8 +246,9 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
     // tables (chirp, Bluestein kernel, K) in its L2
     const int c = blockIdx.x % 8, k = blockIdx.x / 8;
     const int rhs = k % A.nrhs;
-    const int p = 8 * (k / A.nrhs) + c;
-    if (p >= A.npairs) return;
+    const int idx = 8 * (k / A.nrhs) + c;
+    if (idx >= A.nlist) return;
+    const int p = A.plist ? A.plist[idx] : idx;
     const RingPairDev P_ = A.pairs[p];
     const FftLenDev L = A.lens[P_.len_idx];
     const int n = P_.nphi, M = L.M, logM = L.logM, sh = pad_shift(logM);
@@ -228,20 +258,134 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
     const bool anal = (MODE == RING_ANALYSIS || MODE == RING_ITERATE);
     const CR* chirp = L.bluestein ? A.chirp + L.chirp_off : nullptr;
     const CR zero = mk<R>(0, 0);
-    // e^{i m phi0} of the analysis unfold, computed once for the three
-    // fields (m = tid + nt r, the first kRot of them in registers), and the
-    // factor e^{i n phi0} between aliased m of the synthesis fold (-1 on
-    // HEALPix rings, whose phi0 = pi / n, 1 for phi0 = 0)
-    constexpr int kRot = 8;
-    CR rotu[kRot];
-    if (anal) {
+    // split ring (n = 4 i): the buffer holds the length-n spectrum or ring in
+    // natural order (padding i/8 only) and, in turn, the four length-i
+    // Bluestein transforms of size M; blu: whole-ring Bluestein (bit-reversed
+    // slots, chirp factors)
+    constexpr bool split = SPLITK > 0;
+    constexpr int kSplitK = SPLITK > 0 ? SPLITK : 1;
+    const bool blu = L.bluestein && !split;
+    const int shn = split ? 31 : sh;
+    const int i4 = n >> 2;
+    // W^kappa = exp(-2 pi i kappa / n) of this lane's kappa = tid + nt u
+    CR w1[kSplitK];
+    if constexpr (split) {
 #pragma unroll
-        for (int r = 0; r < kRot; ++r) {
-            const int m = tid + nt * r;
-            rotu[r] = m <= mmax ? conjc(phase_rot<R>(m, P_.phi0_den)) : mk<R>(1, 0);
+        for (int u = 0; u < kSplitK; ++u) {
+            const int kap = tid + nt * u;
+            w1[u] = kap < i4 ? unit_root<R>(kap, n) : mk<R>(1, 0);
         }
     }
+    // the factor e^{i n phi0} between aliased m of the synthesis fold (-1 on
+    // HEALPix rings, whose phi0 = pi / n, 1 for phi0 = 0)
     const CR alias_step = phase_rot<R>(n, P_.phi0_den);
+
+    // A split ring's transform between the folded spectrum (natural order,
+    // synthesis) or the ring (analysis) and the spectrum X (natural order):
+    //   DFT(v)_{4 j' + r} = DFT_i(G_r)[j'],  G_r[kap] = W^{r kap} sum_q (-i)^{r q} v_{kap + q i},
+    //   X_{kap + q i} = sum_r (-i)^{r q} W^{r kap} Y_r[kap],  Y_r = DFT_i(t_{4 j' + r}),
+    // with W = exp(-2 pi i / n).  Per r the inverse sub-transform, the pixel
+    // update of pixels 4 j' + r and the forward sub-transform run back to
+    // back; G_r and then W^{r kap} Y_r stay in registers.
+    auto split_ring = [&](int f, int64_t moff) {
+        CR Z[kSplitK][4];
+        auto wpow = [&](int u, int r) {
+            CR w = mk<R>(1, 0);
+            for (int e = 0; e < r; ++e) w = cmul(w, w1[u]);
+            return w;
+        };
+        if (synth) {
+#pragma unroll
+            for (int u = 0; u < kSplitK; ++u) {
+                const int kap = tid + nt * u;
+                if (kap < i4) {
+                    dft4<R>(buf[pidx(kap, shn)], buf[pidx(kap + i4, shn)], buf[pidx(kap + 2 * i4, shn)],
+                         buf[pidx(kap + 3 * i4, shn)], Z[u]);
+#pragma unroll
+                    for (int r = 1; r < 4; ++r) Z[u][r] = cmul(Z[u][r], wpow(u, r));
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (synth) {
+#pragma unroll
+                for (int u = 0; u < kSplitK; ++u) {
+                    const int kap = tid + nt * u;
+                    if (kap < i4) buf[pidx((int)brev(kap, logM), sh)] = cmul(Z[u][r], chirp[kap]);
+                }
+                for (int jj = i4 + tid; jj < M; jj += nt) buf[pidx((int)brev(jj, logM), sh)] = zero;
+                __syncthreads();
+                dft_core<R>(buf, L, A);
+                // x_{4 j' + r} = conj(buf[brev(j')] chirp_j')
+                for (int jp = tid; jp < i4; jp += nt) {
+                    const int q = (int)brev(jp, logM);
+                    const CR y = cmul(buf[pidx(q, sh)], chirp[jp]);
+                    const int j = 4 * jp + r;
+                    const double xn = (double)y.x, xs = -(double)y.y;
+                    if (MODE == RING_SYNTH) {
+                        map_out[moff + P_.off_n + j] = xn;
+                        if (P_.has_s) map_out[moff + P_.off_s + j] = xs;
+                    } else {
+                        const int64_t kn = (int64_t)f * A.npix + P_.off_n + j;
+                        const double tn = Kp[kn] * xn + bp[moff + P_.off_n + j];
+                        double ts = 0.0;
+                        if (P_.has_s) {
+                            const int64_t ks = (int64_t)f * A.npix + P_.off_s + j;
+                            ts = Kp[ks] * xs + bp[moff + P_.off_s + j];
+                        }
+                        if (map_out) {
+                            map_out[moff + P_.off_n + j] = tn;
+                            if (P_.has_s) map_out[moff + P_.off_s + j] = ts;
+                        }
+                        buf[pidx(q, sh)] = cmul(mk<R>((R)tn, (R)ts), chirp[jp]);
+                    }
+                }
+                if (MODE == RING_ITERATE)
+                    for (int jj = i4 + tid; jj < M; jj += nt) buf[pidx((int)brev(jj, logM), sh)] = zero;
+                __syncthreads();
+            } else {
+                for (int q = tid; q < M; q += nt) {
+                    const int jp = (int)brev(q, logM);
+                    CR a = zero;
+                    if (jp < i4) {
+                        const int j = 4 * jp + r;
+                        a.x = (R)map_in[moff + P_.off_n + j];
+                        a.y = P_.has_s ? (R)map_in[moff + P_.off_s + j] : R(0);
+                        a = cmul(a, chirp[jp]);
+                    }
+                    buf[pidx(q, sh)] = a;
+                }
+                __syncthreads();
+            }
+            if (anal) {
+                dft_core<R>(buf, L, A);
+#pragma unroll
+                for (int u = 0; u < kSplitK; ++u) {
+                    const int kap = tid + nt * u;
+                    if (kap < i4) {
+                        const CR y = cmul(buf[pidx((int)brev(kap, logM), sh)], chirp[kap]);
+                        Z[u][r] = r == 0 ? y : cmul(y, wpow(u, r));
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (anal) {
+#pragma unroll
+            for (int u = 0; u < kSplitK; ++u) {
+                const int kap = tid + nt * u;
+                if (kap < i4) {
+                    CR X[4];
+                    dft4<R>(Z[u][0], Z[u][1], Z[u][2], Z[u][3], X);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) buf[pidx(kap + q * i4, shn)] = X[q];
+                }
+            }
+            __syncthreads();
+        }
+    };
 
     for (int f = 0; f < 3; ++f) {
         CP* ph = phase + (((int64_t)rhs * 3 + f) * A.npairs + p) * (mmax + 1) * 2;
@@ -257,9 +401,10 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
             const bool half_turn = P_.phi0_den == n;
             CR rotj = phase_rot<R>(tid, P_.phi0_den);
             const CR rstep = phase_rot<R>(nt, P_.phi0_den);
-            for (int j = tid; j < M; j += nt, rotj = cmul(rotj, rstep)) {
+            const int jend = split ? n : M;
+            for (int j = tid; j < jend; j += nt, rotj = cmul(rotj, rstep)) {
                 CR v = zero;
-                const int k = L.bluestein ? (int)brev(j, logM) : j;   // slot of logical index j
+                const int k = blu ? (int)brev(j, logM) : j;           // slot of logical index j
                 if (j < n) {
                     CR cn = zero, cs = zero;
                     const int w = (j + mmax) / n;
@@ -280,11 +425,15 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
                     }
                     // z = C_N + i C_S ; store conj(z)
                     v = mk<R>(cn.x - cs.y, -(cn.y + cs.x));
-                    if (L.bluestein) v = cmul(v, chirp[j]);
+                    if (blu) v = cmul(v, chirp[j]);
                 }
-                buf[pidx(k, sh)] = v;
+                buf[pidx(k, shn)] = v;
             }
             __syncthreads();
+        }
+        if constexpr (split) {
+            split_ring(f, moff);
+        } else if (synth) {
             idft_core<R>(buf, L, A);
             // now x_j (packed N + i S) = conj(buf[brev(j)] * chirp_j)
             for (int j = tid; j < n; j += nt) {
@@ -317,7 +466,7 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
             }
             __syncthreads();
         }
-        if (MODE == RING_ANALYSIS) {
+        if (MODE == RING_ANALYSIS && !split) {
             for (int q = tid; q < M; q += nt) {
                 const int j = (int)brev(q, logM);
                 CR a = zero;
@@ -331,27 +480,25 @@ __global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* 
             __syncthreads();
         }
         if (anal) {
-            dft_core<R>(buf, L, A);
+            if (!split) dft_core<R>(buf, L, A);
             // unfold: X_N = (Z_k + conj Z_{-k}) / 2,  X_S = (Z_k - conj Z_{-k}) / (2i)
             auto unfold = [&](int m, CR rot) {
                 const int k = m % n;
                 const int k2 = (n - k) % n;
-                const int q1 = L.bluestein ? (int)brev(k, logM) : k;
-                const int q2 = L.bluestein ? (int)brev(k2, logM) : k2;
-                CR z1 = buf[pidx(q1, sh)], z2 = buf[pidx(q2, sh)];
-                if (L.bluestein) { z1 = cmul(z1, chirp[k]); z2 = cmul(z2, chirp[k2]); }
+                const int q1 = blu ? (int)brev(k, logM) : k;
+                const int q2 = blu ? (int)brev(k2, logM) : k2;
+                CR z1 = buf[pidx(q1, shn)], z2 = buf[pidx(q2, shn)];
+                if (blu) { z1 = cmul(z1, chirp[k]); z2 = cmul(z2, chirp[k2]); }
                 const CR xn = mk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
                 const CR xs = mk<R>(R(0.5) * (z1.y + z2.y), R(-0.5) * (z1.x - z2.x));
                 const CR on = cmul(xn, rot), os = cmul(xs, rot);
                 ph[2 * m] = mk<P>((P)on.x, (P)on.y);
                 ph[2 * m + 1] = P_.has_s ? mk<P>((P)os.x, (P)os.y) : mk<P>(0, 0);
             };
-#pragma unroll
-            for (int r = 0; r < kRot; ++r) {
-                const int m = tid + nt * r;
-                if (m <= mmax) unfold(m, rotu[r]);
-            }
-            for (int m = tid + nt * kRot; m <= mmax; m += nt) unfold(m, conjc(phase_rot<R>(m, P_.phi0_den)));
+            // e^{-i m phi0} for m = tid, tid + nt, ...: one rotation per step
+            CR rot = conjc(phase_rot<R>(tid, P_.phi0_den));
+            const CR ustep = conjc(phase_rot<R>(nt, P_.phi0_den));
+            for (int m = tid; m <= mmax; m += nt, rot = cmul(rot, ustep)) unfold(m, rot);
             __syncthreads();
         }
     }
@@ -361,6 +508,8 @@ template <typename R>
 RingArgs<R> ring_args(dm_plan* p, const void* chirp, const void* bhat, const void* tw) {
     RingArgs<R> A;
     A.npairs = p->npairs;
+    A.plist = nullptr;
+    A.nlist = p->npairs;
     A.mmax = p->mmax;
     int lm = 0;
     while ((1 << lm) < p->fft.Mmax) ++lm;
@@ -374,39 +523,71 @@ RingArgs<R> ring_args(dm_plan* p, const void* chirp, const void* bhat, const voi
     return A;
 }
 
+template <int MODE, int SPLITK, typename R, typename P>
+void launch_mode(const RingArgs<R>& A, int nlist, const int* plist, int lds_elems, int threads,
+                 const double* map_in, double* map_out, const double* K, const double* b, C2<P>* ph, hipStream_t s) {
+    if (nlist <= 0) return;
+    RingArgs<R> Ar = A;
+    Ar.plist = plist;
+    Ar.nlist = nlist;
+    const dim3 grid((unsigned)(((nlist + 7) / 8) * 8 * A.nrhs));
+    const size_t lds = (size_t)(lds_elems + lds_elems / 8 + 8) * sizeof(C2<R>);
+    hipLaunchKernelGGL((ring_kernel<MODE, SPLITK, R, P>), grid, dim3(threads), lds, s, Ar, map_in, map_out, K, b, ph);
+}
+
+// one launch over every ring pair, or (with split rings) one over the
+// others and one over the split rings
+template <int MODE, typename R, typename P>
+void launch_both(dm_plan* p, const RingArgs<R>& A, const double* map_in, double* map_out, const double* K,
+                 const double* b, C2<P>* ph, hipStream_t s) {
+    if (p->n_split == 0) {
+        launch_mode<MODE, 0, R, P>(A, p->npairs, nullptr, p->fft.lds_elems, p->fft_threads, map_in, map_out, K, b,
+                                   ph, s);
+        return;
+    }
+    launch_mode<MODE, 0, R, P>(A, p->n_whole, p->d_plist_whole, p->fft.lds_elems, p->fft_threads, map_in, map_out,
+                               K, b, ph, s);
+    if (p->split_k <= 2)
+        launch_mode<MODE, 2, R, P>(A, p->n_split, p->d_plist_split, p->fft.lds_split, p->fft_threads, map_in,
+                                   map_out, K, b, ph, s);
+    else
+        launch_mode<MODE, 4, R, P>(A, p->n_split, p->d_plist_split, p->fft.lds_split, p->fft_threads, map_in,
+                                   map_out, K, b, ph, s);
+}
+
 template <typename R, typename P>
 void launch_ring_t(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
                    const double* b, void* phase, const RingArgs<R>& A, hipStream_t s) {
     C2<P>* ph = static_cast<C2<P>*>(phase);
     RingArgs<R> Ar = A;
     Ar.nrhs = nrhs;
-    dim3 grid((unsigned)(((p->npairs + 7) / 8) * 8 * nrhs));
-    dim3 block(p->fft_threads);
-    const size_t lds = (size_t)(p->fft.Mmax + p->fft.Mmax / 8 + 8) * sizeof(C2<R>);
     switch (mode) {
-        case RING_ANALYSIS:
-            hipLaunchKernelGGL((ring_kernel<RING_ANALYSIS, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
-            break;
-        case RING_SYNTH:
-            hipLaunchKernelGGL((ring_kernel<RING_SYNTH, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
-            break;
-        default:
-            hipLaunchKernelGGL((ring_kernel<RING_ITERATE, R, P>), grid, block, lds, s, Ar, map_in, map_out, K, b, ph);
-            break;
+        case RING_ANALYSIS: launch_both<RING_ANALYSIS, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
+        case RING_SYNTH: launch_both<RING_SYNTH, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
+        default: launch_both<RING_ITERATE, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
     }
+}
+
+template <int MODE, int SPLITK, typename R, typename P>
+hipError_t set_lds_one(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<MODE, SPLITK, R, P>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int SPLITK, typename R, typename P>
+hipError_t set_lds_modes(size_t bytes) {
+    hipError_t e = set_lds_one<RING_ANALYSIS, SPLITK, R, P>(bytes);
+    if (e == hipSuccess) e = set_lds_one<RING_SYNTH, SPLITK, R, P>(bytes);
+    if (e == hipSuccess) e = set_lds_one<RING_ITERATE, SPLITK, R, P>(bytes);
+    return e;
 }
 
 template <typename R, typename P>
 hipError_t set_lds_t(size_t bytes) {
-    hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_ANALYSIS, R, P>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_SYNTH, R, P>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<RING_ITERATE, R, P>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e = set_lds_modes<0, R, P>(bytes);
+    if (e == hipSuccess) e = set_lds_modes<2, R, P>(bytes);
+    if (e == hipSuccess) e = set_lds_modes<4, R, P>(bytes);
+    return e;
 }
 
 }  // namespace

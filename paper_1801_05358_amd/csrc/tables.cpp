@@ -249,26 +249,38 @@ static int ilog2(int v) {
     return r;
 }
 
-bool build_fft_tables(const RingTables& rt, int mmax, FftTables& ft, std::string& err) {
+// A Bluestein length n = 4 i is split into four length-i DFTs when its own
+// Bluestein buffer (a power of two >= 2n - 1) exceeds max_elems, the
+// largest buffer one workgroup's LDS holds: the split needs max(n, M_i)
+// elements instead (at Nside 2048: 8188 instead of 16384).
+bool build_fft_tables(const RingTables& rt, int mmax, int max_elems, FftTables& ft, std::string& err) {
     (void)mmax;
     ft = FftTables();
     std::vector<int> lens(rt.nphi.begin(), rt.nphi.end());
     std::sort(lens.begin(), lens.end());
     lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+    auto blue = [](int v) { return 1 << ilog2(2 * v - 1); };
     int64_t coff = 0, boff = 0;
     for (int n : lens) {
         const bool pow2 = (n & (n - 1)) == 0;
-        const int M = pow2 ? n : (1 << ilog2(2 * n - 1));
+        const bool split = !pow2 && n % 4 == 0 && blue(n) > max_elems;
+        const int nb = split ? n / 4 : n;              // Bluestein length
+        const int M = pow2 ? n : blue(nb);
         ft.n.push_back(n);
+        ft.split.push_back(split ? 1 : 0);
         ft.M.push_back(M);
         ft.logM.push_back(ilog2(M));
         ft.chirp_off.push_back(pow2 ? -1 : coff);
         ft.bhat_off.push_back(pow2 ? -1 : boff);
         if (!pow2) {
-            coff += n;
+            coff += nb;
             boff += M;
         }
         ft.Mmax = std::max(ft.Mmax, M);
+        if (split)
+            ft.lds_split = std::max(ft.lds_split, std::max(n, M));
+        else
+            ft.lds_elems = std::max(ft.lds_elems, M);
     }
     ft.chirp.assign(2 * coff, 0.0);
     ft.bhat.assign(2 * boff, 0.0);
@@ -276,7 +288,7 @@ bool build_fft_tables(const RingTables& rt, int mmax, FftTables& ft, std::string
     auto work = [&](int t, int nt) {
         for (int i = t; i < nl; i += nt) {
             if (ft.chirp_off[i] < 0) continue;
-            const int n = ft.n[i], M = ft.M[i];
+            const int n = ft.split[i] ? ft.n[i] / 4 : ft.n[i], M = ft.M[i];
             std::vector<std::complex<ld>> b(M, std::complex<ld>(0, 0));
             for (int j = 0; j < n; ++j) {
                 const int64_t r = ((int64_t)j * j) % (2 * (int64_t)n);   // exact j^2 mod 2n
