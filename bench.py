@@ -24,6 +24,7 @@ Prints one JSON line.  Usage:
 """
 
 import argparse
+import gc
 import csv
 import hashlib
 import json
@@ -192,8 +193,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--nside", type=int, default=1024)
-    ap.add_argument("--lmax", type=int, default=2048)
+    ap.add_argument("--cfg", type=int, default=3, choices=[2, 3, 4, 5],
+                    help="workload recipe (mask, noise, sizes) of configuration 2..5; 3 is the metric's")
+    ap.add_argument("--nside", type=int, default=None, help="override the configuration's Nside")
+    ap.add_argument("--lmax", type=int, default=None, help="override the configuration's lmax")
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--noise", choices=["diag", "corr"], default="diag",
@@ -217,16 +220,18 @@ def main():
     import torch
     from paper_1801_05358_amd import dmwf, inputs
 
-    nside, lmax, B = args.nside, args.lmax, args.nrhs
+    cfg = args.cfg
+    B = args.nrhs
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    log(f"[bench] workload nside={nside} lmax={lmax} nrhs={B} precision={args.precision}")
     corr = args.noise == "corr"
     if corr:
-        prob = inputs.correlated_problem(3, nside=nside, lmax=lmax)
+        prob = inputs.correlated_problem(cfg, nside=args.nside, lmax=args.lmax)
         ncov, obs = prob["ncov6"], (prob["obs_t"], prob["obs_p"])
     else:
-        prob = inputs.make_problem(3, nside=nside, lmax=lmax)
+        prob = inputs.make_problem(cfg, nside=args.nside, lmax=args.lmax)
         ncov, obs = prob["ncov"], prob["obs"]
+    nside, lmax = prob["nside"], prob["lmax"]
+    log(f"[bench] workload cfg={cfg} nside={nside} lmax={lmax} nrhs={B} precision={args.precision}")
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
@@ -245,11 +250,11 @@ def main():
     prec = dmwf.MIXED if args.precision == "mixed" else dmwf.FP64
     plan = make_plan(prec, B)
     # synthetic data d = Y s + n, made with the library's own synthesis
-    s = np.stack([inputs.signal_alm(3, lmax, k) for k in range(B)])
+    s = np.stack([inputs.signal_alm(cfg, lmax, k) for k in range(B)])
     alm_t = torch.from_numpy(s.view(np.float64).reshape(B, 3, -1)).to(dev)
     d_t = torch.empty((B, 3, plan.npix), dtype=torch.float64, device=dev)
     plan.alm2map_device(alm_t, d_t, stream=stream)
-    noise = np.stack([inputs.noise_map6(3, ncov, prob["obs3"], k) if corr else inputs.noise_map(3, ncov, obs, k)
+    noise = np.stack([inputs.noise_map6(cfg, ncov, prob["obs3"], k) if corr else inputs.noise_map(cfg, ncov, obs, k)
                       for k in range(B)])
     d_t += torch.from_numpy(noise).to(dev)
     del noise
@@ -287,9 +292,10 @@ def main():
         bound, peak = "mfma", PEAK["fp64_mfma"]
     else:
         bound, peak = "alu", PEAK["fp64_valu"]
-    traffic = read_traffic(dom, args.precision, B) if (nside, lmax) == (1024, 2048) else None
+    traffic = read_traffic(dom, args.precision, B) if (cfg, nside, lmax, corr) == (3, 1024, 2048, False) else None
     ring_ms, ring_n = kt["ring_fft_pointwise"]
     rb = ring_bytes(plan.npix, plan.nrings, lmax, B)
+    band, holes, dyn = prob["band"], prob["holes"], prob["dyn"]
     prec_text = ("mixed: FP32 matrix-core contraction, FP64 recursion, FFT and iterate"
                  if args.precision == "mixed" else "FP64 throughout")
     rec = {
@@ -299,13 +305,16 @@ def main():
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"HEALPix Nside {nside}, lmax {lmax}, " + (
-                               "T mask |b|<15 deg + 2000 holes, P mask |b|<12 deg + 1000 other holes, "
-                               "correlated 3x3 scan noise 100:1 (Q = U = 2 T, correlations .3/-.15/.2), "
+                               f"T mask |b|<{band:.4g} deg + {2 * holes} holes, P mask |b|<{band - 3:.4g} deg + "
+                               f"{holes} other holes, correlated 3x3 scan noise {dyn:g}:1 (Q = U = 2 T, "
+                               f"correlations .3/-.15/.2), "
                                if corr else
-                               "mask |b|<15 deg + 1000 holes of 0.5 deg, scan noise 100:1 (Q = U = 2 T), ") +
+                               f"mask |b|<{band:.4g} deg + {holes} holes of 0.5 deg, scan noise {dyn:g}:1 "
+                               f"(Q = U = 2 T), ") +
                                f"cooling lambda 1e3 -> 1 in steps of 10 "
                                f"iterations, {B} right-hand sides per launch ({prec_text})",
-                   "nside": nside, "lmax": lmax, "nrhs": B, "precision": args.precision, "noise": args.noise},
+                   "recipe": f"configuration {cfg}", "nside": nside, "lmax": lmax, "nrhs": B,
+                   "precision": args.precision, "noise": args.noise},
         "solve_iterations_per_s": round(its, 4),
         "rhs_iterations_per_s": round(B * its, 3),
         "roofline": {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
@@ -316,6 +325,12 @@ def main():
                          "unit": "GB/s"},
     }
 
+    # the timed plan's device memory goes back before the reference plans
+    # are made (at Nside 2048 two 8-RHS plans do not fit together)
+    nalm = plan.nalm
+    del plan
+    gc.collect()
+    torch.cuda.synchronize()
     if not args.no_check:
         # the same RHS through the plain FP64 path, same schedule
         if args.precision == "mixed":
@@ -330,7 +345,7 @@ def main():
             tr = time.perf_counter() - t1
             x = out_t.cpu().numpy().view(np.complex128).reshape(B, 3, -1)
             r = ref_t.cpu().numpy().view(np.complex128).reshape(B, 3, -1)
-            tot, worst = field_errors(x, r, plan.nalm, lmax)
+            tot, worst = field_errors(x, r, nalm, lmax)
             rec["accuracy"] = {"reference": f"FP64 GPU path, same {B} RHS and schedule",
                                "rel_l2_T_E_B": [float(f"{v:.3e}") for v in tot],
                                "worst_l_bin_T_E_B": [float(f"{v:.3e}") for v in worst],

@@ -263,11 +263,12 @@ def test_input_errors(dmwf):
     assert np.array_equal(plan.wiener_filter(d)["alm"], plan.wiener_filter(d2)["alm"])
 
 
-@pytest.mark.parametrize("nside,lmax", [(256, 512), (1024, 2048)])
+@pytest.mark.parametrize("nside,lmax", [(256, 512), (1024, 2048), (2048, 4096)])
 def test_full_size_sampled_transforms(nside, lmax, dmwf):
-    """Configs 2 and 3 geometry at full size: synthesis on sampled rings
-    (polar, cap/belt boundary, equator, south) and analysis on sampled
-    (l, m), each computed one by one by the oracle."""
+    """Configs 2, 3 and 5 geometry at full size: synthesis on sampled rings
+    (polar, cap/belt boundary, equator, south; at Nside 2048 also rings
+    whose transform is split into four quarter-length ones) and analysis on
+    sampled (l, m), each computed one by one by the oracle."""
     print(f"full-size sampled nside={nside} lmax={lmax}", flush=True)
     rng = np.random.default_rng(nside)
     grid = healpix_grid(nside)
@@ -276,7 +277,7 @@ def test_full_size_sampled_transforms(nside, lmax, dmwf):
     a = inputs.draw_signal(inputs.spectra(lmax), lmax, rng)
     mp = plan.alm2map(a)
     nr = 4 * nside - 1
-    rings = [0, 1, nside - 1, nside, 2 * nside - 1, 3 * nside, nr - 1]
+    rings = [0, 1, 3 * nside // 4, nside - 2, nside - 1, nside, 2 * nside - 1, 3 * nside, nr - nside + 1, nr - 1]
     for r, blk in zip(rings, sht.synthesis(a, rings=rings)):
         o, n = grid["offset"][r], grid["nphi"][r]
         err = np.abs(mp[:, o:o + n] - blk).max()
