@@ -276,6 +276,56 @@ void sync_plan_stream_to(dm_plan* p, hipStream_t s) {
     HIPCHK(hipEventDestroy(e));
 }
 
+// Fixed-mode cooling steps run as HIP graphs: the step's iterations (all but
+// the solve's last) are recorded on the plan's own stream (capture is not
+// possible on the legacy default stream a caller may pass) and launched on
+// s.  The executable graphs are kept until the solve has synchronised.
+// Profiling (per-kernel events) and DMWF_GRAPHS=0 run the launches directly.
+struct StepGraphs {
+    hipStream_t s;
+    std::vector<hipGraphExec_t> keep;
+    explicit StepGraphs(hipStream_t st) : s(st) {}
+    ~StepGraphs() {
+        if (keep.empty()) return;
+        (void)hipStreamSynchronize(s);          // every launch has finished (also on error paths)
+        for (hipGraphExec_t e : keep) (void)hipGraphExecDestroy(e);
+    }
+};
+
+void messenger_step(dm_plan* p, int nrhs, double* t_out, hipStream_t s);
+
+void run_iterations(dm_plan* p, int nrhs, const double* F, double* alm, int count, hipStream_t s, StepGraphs& g) {
+    auto body = [&](hipStream_t st) {
+        for (int i = 0; i < count; ++i) {
+            // t_hat = A t ; u = F t_hat   (eq 8) ; u_x = Y u ; t = K u_x + b ; next t_hat's ring data (eq 9)
+            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, st);
+            leg_synthesis(p, nrhs, p->d_alm_spin, st);
+            messenger_step(p, nrhs, nullptr, st);
+        }
+    };
+    if (count <= 0) return;
+    if (!p->graphs || p->profiling || count < 2) {
+        body(s);
+        return;
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        body(p->stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(p->stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(p->stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t st = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(st);
+    g.keep.push_back(exec);
+    HIPCHK(hipGraphLaunch(exec, s));
+}
+
 // fingerprint of a device buffer (blocks on s)
 uint64_t device_hash(dm_plan* p, const void* buf, int64_t n, int elem_bytes, hipStream_t s) {
     uint64_t* acc = reinterpret_cast<uint64_t*>(p->d_red + 8);
@@ -323,6 +373,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     const int64_t alm_len = (int64_t)nrhs * 3 * p->nalm * 2;
     const size_t alm_bytes = (size_t)alm_len * sizeof(double);
     if (resumable) p->state.valid = false;
+    StepGraphs graphs(s);
 
     // setup: d0 = mask(d), b = T N^-1 d0
     HIPCHK(launch_data_setup(p, nrhs, d, p->d_d0, p->d_b, s));
@@ -370,21 +421,23 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         const int64_t full = (int64_t)nsteps * niter;
         const int64_t end = p->sched.max_iters > 0 ? std::min<int64_t>(full, p->sched.max_iters) : full;
         if (rs) restart_from_u(total >= end);
-        for (int64_t it = total; it < end; ++it) {
-            const double* F = p->d_filters + per * (it / niter);
-            const bool last = (it == end - 1);
-            // the previous iterate, for the final Cauchy ratio
-            if (last) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
-            // t_hat = A t ; u = F t_hat        (eq 8)
-            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
-            // u_x = Y u                          (synthesis)
-            leg_synthesis(p, nrhs, p->d_alm_spin, s);
-            if (!last) {
-                // t = K u_x + b ; next t_hat's ring Fourier data   (eq 9)
-                messenger_step(p, nrhs, nullptr, s);
-            } else {
-                ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+        for (int64_t it = total; it < end;) {
+            const int64_t k = it / niter;
+            const double* F = p->d_filters + per * k;
+            // this cooling step's iterations before the solve's last one
+            const int64_t stop = std::min<int64_t>((k + 1) * niter, end - 1);
+            if (it < stop) {
+                run_iterations(p, nrhs, F, alm, (int)(stop - it), s, graphs);
+                it = stop;
+                continue;
             }
+            // the last iteration: keep the previous iterate (final Cauchy
+            // ratio) and end with u_x = Y u
+            HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
+            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
+            leg_synthesis(p, nrhs, p->d_alm_spin, s);
+            ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+            ++it;
         }
         total = std::max(total, end);
         finished = total >= full;
@@ -637,6 +690,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
                 "ring length needs a transform buffer of " + std::to_string(lds_max) +
                     " points, beyond the LDS of one workgroup in double precision");
         HIPCHK(hipStreamCreate(&p->stream));
+        p->graphs = env_int("DMWF_GRAPHS", 1) != 0;
 
         // ring and pair tables
         std::vector<double> px(p->npairs), pw(p->npairs), one(p->npairs, 1.0);

@@ -196,6 +196,7 @@ struct dm_plan {
 
     // timing
     bool profiling = false;
+    bool graphs = true;                // fixed-mode cooling steps as HIP graphs (DMWF_GRAPHS=0: off)
     double kc_ms[dmwf::KC_COUNT] = {0, 0, 0, 0, 0};
     int64_t kc_n[dmwf::KC_COUNT] = {0, 0, 0, 0, 0};
     dmwf::GpuEvents ev;
