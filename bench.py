@@ -262,6 +262,8 @@ def main():
     torch.cuda.synchronize()
     log("[bench] inputs resident")
 
+    tune = plan.autotune(B)
+    log(f"[bench] autotune {tune}")
     if args.warmup > 0:
         set_iters(plan, args.warmup)
         plan.wiener_filter_device(d_t, out_t, stream=stream)
@@ -330,6 +332,7 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": traffic},
         "kernels_ms_avg": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
+        "autotune": {"syn_mchunk": tune["syn_mchunk"], "ana_mchunk": tune["ana_mchunk"]},
         "ring_fft_hbm": {"achieved": round(rb / (ring_ms / max(ring_n, 1) * 1e-3) / 1e9, 1), "peak": HBM_PEAK,
                          "unit": "GB/s"},
     }

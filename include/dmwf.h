@@ -262,6 +262,22 @@ dm_status dm_iterate(dm_plan* plan, int nrhs, const double* d, const double* t_i
 dm_status dm_checkpoint_save(const dm_plan* plan, const char* path);
 dm_status dm_checkpoint_load(dm_plan* plan, const char* path);
 
+/* Autotuner of the batched matrix-core Legendre kernels: for nrhs right-hand
+ * sides (a count that uses them: from 2 on for DM_MIXED, 8 for DM_FP64)
+ * it times each kernel with every candidate m-chunk (how many consecutive m
+ * a chunk of workgroups on one XCD covers: 0, 1, 2, 4, 8) on the plan's own
+ * buffers and keeps the fastest for this plan.  The choice changes only
+ * which XCD runs which workgroup, never the arithmetic: results stay the
+ * same to the last bit.  chunks (nullable, [2]) receives the synthesis and
+ * analysis m-chunk, ms (nullable, [2]) their times per launch (0 when the
+ * choice came from the cache).  With the environment variable
+ * DMWF_TUNE_CACHE naming a file, choices are looked up there first (key:
+ * grid, lmax, precision, nrhs column tiles) and new ones appended.  Leaves
+ * the plan unchanged (DM_OK, chunks = current values, ms = 0) when nrhs does
+ * not use the batched kernels.  Call between solves; it overwrites the
+ * plan's transform work buffers.                                          */
+dm_status dm_autotune(dm_plan* plan, int nrhs, int* chunks, double* ms);
+
 /* Per-kernel GPU timing, measured with HIP events on the plan's stream
  * when enabled: enable != 0 turns recording on and clears the totals.
  * dm_kernel_times writes, for kernel class k < *count (0 Legendre

@@ -1383,6 +1383,87 @@ dm_status dm_iterate(dm_plan* p, int nrhs, const double* d, const double* t_in, 
     });
 }
 
+dm_status dm_autotune(dm_plan* p, int nrhs, int* chunks, double* ms) {
+    return guarded(p, [&] {
+        check_rhs(p, nrhs);
+        if (ms) ms[0] = ms[1] = 0.0;
+        if (!use_mfma(p, nrhs)) {
+            if (chunks) { chunks[0] = p->syn_mchunk; chunks[1] = p->ana_mchunk; }
+            return;
+        }
+        // cache key: grid, lmax, precision, column tiles of 8 RHS
+        char key[160];
+        std::snprintf(key, sizeof key, "g%d_%d_%d_%d_l%d_p%d_t%d", p->grid.kind, p->grid.nside, p->grid.ntheta,
+                      p->grid.nphi, p->lmax, (int)p->precision, (nrhs + 7) / 8);
+        const char* cache = std::getenv("DMWF_TUNE_CACHE");
+        if (cache && cache[0]) {
+            if (std::FILE* f = std::fopen(cache, "r")) {
+                char k[160];
+                int a = -1, b = -1;
+                bool hit = false;
+                while (std::fscanf(f, "%159s %d %d", k, &a, &b) == 3)
+                    if (std::strcmp(k, key) == 0 && a >= 0 && a <= 16 && b >= 0 && b <= 16) {
+                        p->syn_mchunk = a;
+                        p->ana_mchunk = b;
+                        hit = true;
+                    }
+                std::fclose(f);
+                if (hit) {
+                    if (chunks) { chunks[0] = p->syn_mchunk; chunks[1] = p->ana_mchunk; }
+                    return;
+                }
+            }
+        }
+        HIPCHK(hipStreamSynchronize(p->stream));
+        const void* phase = phase_of(p, nrhs);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        struct Ev2 {
+            hipEvent_t a, b;
+            ~Ev2() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+        } guard{e0, e1};
+        // best of three launches after a warm-up
+        auto timeit = [&](auto launch) {
+            HIPCHK(launch());
+            float best = 1e30f;
+            for (int r = 0; r < 3; ++r) {
+                HIPCHK(hipEventRecord(e0, p->stream));
+                HIPCHK(launch());
+                HIPCHK(hipEventRecord(e1, p->stream));
+                HIPCHK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                best = std::min(best, t);
+            }
+            return (double)best;
+        };
+        const int cand[] = {0, 1, 2, 4, 8};
+        double best_syn = 1e300, best_ana = 1e300;
+        int syn = p->syn_mchunk, ana = p->ana_mchunk;
+        p->mfma_nct = 1;
+        for (int c : cand) {
+            p->syn_mchunk = c;
+            const double t = timeit([&] { return launch_bsyn(p, nrhs, p->d_alm_spin, const_cast<void*>(phase), p->stream); });
+            if (t < best_syn) { best_syn = t; syn = c; }
+        }
+        for (int c : cand) {
+            p->ana_mchunk = c;
+            const double t = timeit([&] { return launch_bana(p, nrhs, phase, p->d_pair_w, p->d_partial, p->stream); });
+            if (t < best_ana) { best_ana = t; ana = c; }
+        }
+        p->syn_mchunk = syn;
+        p->ana_mchunk = ana;
+        if (chunks) { chunks[0] = syn; chunks[1] = ana; }
+        if (ms) { ms[0] = best_syn; ms[1] = best_ana; }
+        if (cache && cache[0])
+            if (std::FILE* f = std::fopen(cache, "a")) {
+                std::fprintf(f, "%s %d %d\n", key, syn, ana);
+                std::fclose(f);
+            }
+    });
+}
+
 dm_status dm_profile_enable(dm_plan* p, int enable) {
     return guarded(p, [&] {
         HIPCHK(hipStreamSynchronize(p->stream));

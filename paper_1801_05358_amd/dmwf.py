@@ -89,6 +89,7 @@ def lib():
         "dm_map2alm_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
         "dm_set_noise_masks": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
                                               ctypes.POINTER(ctypes.c_uint8)]),
+        "dm_autotune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
         "dm_checkpoint_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "dm_checkpoint_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "dm_iterate": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]),
@@ -110,7 +111,7 @@ def exported_symbols():
             "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_wiener_filter",
             "dm_wiener_filter_device",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
-            "dm_map2alm_device", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
+            "dm_map2alm_device", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
 
 
 def device_count():
@@ -215,6 +216,14 @@ class Plan:
         s = DmSchedule(float(lambda_start), 0, 0, float(beta), float(eps_start), float(eps_end), float(eta),
                        int(max_iters))
         self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
+
+    def autotune(self, nrhs):
+        """Pick the batched Legendre kernels' m-chunks for nrhs RHS; returns
+        dict(syn_mchunk, ana_mchunk, syn_ms, ana_ms)."""
+        ch = (ctypes.c_int * 2)()
+        ms = (ctypes.c_double * 2)()
+        self._check(lib().dm_autotune(self._h, int(nrhs), ch, ms))
+        return dict(syn_mchunk=ch[0], ana_mchunk=ch[1], syn_ms=ms[0], ana_ms=ms[1])
 
     def checkpoint_save(self, path):
         """Write where the last Wiener filter solve stopped to path."""
