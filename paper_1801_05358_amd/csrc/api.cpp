@@ -163,9 +163,12 @@ bool use_mfma(dm_plan* p, int nrhs) {
     return nrhs >= (p->precision == DM_MIXED ? 2 : 8);
 }
 
-// the batched kernels carry scaled recursions; their scales enter the
+// the Legendre kernels carry scaled recursions; their scales enter the
 // combine step and the spin-basis copy
-const double* spin_scales(dm_plan* p, int nrhs) { return use_mfma(p, nrhs) ? p->d_scale : nullptr; }
+const double* spin_scales(dm_plan* p, int nrhs) {
+    (void)nrhs;
+    return p->d_scale;
+}
 
 void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, double* alm, double* spin,
                   hipStream_t s, double* cpart = nullptr) {

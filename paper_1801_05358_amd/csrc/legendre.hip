@@ -49,7 +49,8 @@ struct LegArgs {
     int lmax, mmax, npairs;
     int64_t nalm;
     const double* __restrict__ pair_x;
-    const double* __restrict__ coef;
+    const double* __restrict__ coef;    // scaled recursions, [nalm][kCoefSStride]
+    const double* __restrict__ scale;   // their scales S, [nalm][2]
     const int* __restrict__ lstart;
     const double* __restrict__ seed;
     int64_t sstride;      // (mmax + 1) * npairs
@@ -62,7 +63,8 @@ LegArgs leg_args(dm_plan* p) {
     a.npairs = p->npairs;
     a.nalm = p->nalm;
     a.pair_x = p->d_pair_x;
-    a.coef = p->d_coef;
+    a.coef = p->d_coef_s;
+    a.scale = p->d_scale;
     a.lstart = p->d_lstart;
     a.seed = p->d_seed;
     a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
@@ -142,18 +144,21 @@ __global__ void seed_kernel(int lmax, int npairs, const double* __restrict__ pai
     for (int k = 0; k < 6; ++k) seed[k * sstride + o] = v[k];
 }
 
-// One recursion step to degree l for R ring pairs: lam (l0, l1),
-// p = (+2)lam (w0, w1), q = (-2)lam (q0, q1) hold degrees (l-2, l-1).
+// One step to degree l of the scaled recursions (mu = lam / S, the degree
+// l-2 term with coefficient 1; the combine step and the spin-basis copy
+// apply S) for R ring pairs: lam (l0, l1), p = (+2)lam (w0, w1),
+// q = (-2)lam (q0, q1) hold degrees (l-2, l-1).
 template <int R>
 __device__ __forceinline__ void advance(const double* __restrict__ c, const double* x, double* l0,
                                         double* l1, double* w0, double* w1, double* q0, double* q1) {
-    const double A0 = c[0], B0 = c[1], al = c[2], ab = c[3], ga = c[4];
+    const double A0 = c[0], al = c[1], ab = c[2];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double ax = A0 * x[r], bx = al * x[r];
-        const double nl = ax * l1[r] - B0 * l0[r];
-        const double nw = (bx + ab) * w1[r] - ga * w0[r];
-        const double nq = (bx - ab) * q1[r] - ga * q0[r];
+        const double ax = A0 * x[r];
+        const double cw = al * x[r] + ab, cq = al * x[r] - ab;
+        const double nl = ax * l1[r] - l0[r];
+        const double nw = cw * w1[r] - w0[r];
+        const double nq = cq * q1[r] - q0[r];
         l0[r] = l1[r]; l1[r] = nl;
         w0[r] = w1[r]; w1[r] = nw;
         q0[r] = q1[r]; q1[r] = nq;
@@ -165,24 +170,27 @@ template <int R>
 __device__ __forceinline__ void activate(const LegArgs& A, int m, int l, const int* ls, const int* pr,
                                          double* l0, double* l1, double* w0, double* w1, double* q0,
                                          double* q1) {
+    // seeds lam at (l-1, l) become mu = lam / S (a degree below m holds 0)
+    const double* sc = A.scale + mbase(m, A.lmax) * 2;
+    auto inv = [&](int d, int k) { return 1.0 / sc[(int64_t)min(max(d, m), A.lmax) * 2 + k]; };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t o = (int64_t)m * A.npairs + pr[r];
         if (l == ls[r]) {
-            l0[r] = A.seed[0 * A.sstride + o];
-            l1[r] = A.seed[1 * A.sstride + o];
+            l0[r] = A.seed[0 * A.sstride + o] * inv(l - 1, 0);
+            l1[r] = A.seed[1 * A.sstride + o] * inv(l, 0);
             if (m >= 2) {
-                w0[r] = A.seed[2 * A.sstride + o];
-                w1[r] = A.seed[3 * A.sstride + o];
-                q0[r] = A.seed[4 * A.sstride + o];
-                q1[r] = A.seed[5 * A.sstride + o];
+                w0[r] = A.seed[2 * A.sstride + o] * inv(l - 1, 1);
+                w1[r] = A.seed[3 * A.sstride + o] * inv(l, 1);
+                q0[r] = A.seed[4 * A.sstride + o] * inv(l - 1, 1);
+                q1[r] = A.seed[5 * A.sstride + o] * inv(l, 1);
             }
         }
         if (m < 2 && l == 2 && ls[r] <= A.lmax) {
-            w0[r] = A.seed[2 * A.sstride + o];
-            w1[r] = A.seed[3 * A.sstride + o];
-            q0[r] = A.seed[4 * A.sstride + o];
-            q1[r] = A.seed[5 * A.sstride + o];
+            w0[r] = A.seed[2 * A.sstride + o] * inv(1, 1);
+            w1[r] = A.seed[3 * A.sstride + o] * inv(2, 1);
+            q0[r] = A.seed[4 * A.sstride + o] * inv(1, 1);
+            q1[r] = A.seed[5 * A.sstride + o] * inv(2, 1);
         }
     }
 }
@@ -221,7 +229,7 @@ template <int R, int PAR, bool ADV, bool ACT>
 __device__ __forceinline__ void synth_step(const LegArgs& A, int m, int l, const double* __restrict__ cf,
                                            const double2* __restrict__ aT, const double2* __restrict__ aP,
                                            const double2* __restrict__ aM, RecState<R>& S, double (&acc)[R][20]) {
-    if (ADV) advance<R>(cf + (int64_t)l * kCoefStride, S.x, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
+    if (ADV) advance<R>(cf + (int64_t)l * kCoefSStride, S.x, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
     if (ACT) activate<R>(A, m, l, S.ls, S.pr, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
     const double2 t = aT[l], e = aP[l], b = aM[l];
     constexpr int o = PAR * 10;
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2
     const double2* __restrict__ aT = alm + (int64_t)rhs * 3 * A.nalm + base;
     const double2* __restrict__ aP = aT + A.nalm;
     const double2* __restrict__ aM = aP + A.nalm;
-    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const double* __restrict__ cf = A.coef + base * kCoefSStride;
     const int nt = blockDim.x, tid = threadIdx.x;
 
     RecState<R> S;
@@ -341,7 +349,7 @@ struct AnaData {
 template <int R, int PAR, bool ADV, bool ACT>
 __device__ __forceinline__ void ana_step(const LegArgs& A, int m, int l, const double* __restrict__ cf,
                                          RecState<R>& S, const AnaData<R>& D, double* slot) {
-    if (ADV) advance<R>(cf + (int64_t)l * kCoefStride, S.x, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
+    if (ADV) advance<R>(cf + (int64_t)l * kCoefSStride, S.x, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
     if (ACT) activate<R>(A, m, l, S.ls, S.pr, S.l0, S.l1, S.w0, S.w1, S.q0, S.q1);
     double c[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -413,7 +421,7 @@ __global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, co
     const int nrhs = gridDim.z;
     const int lmax = A.lmax;
     const int64_t base = mbase(m, lmax);
-    const double* __restrict__ cf = A.coef + base * kCoefStride;
+    const double* __restrict__ cf = A.coef + base * kCoefSStride;
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * (kAnaThreads / 64) + (threadIdx.x >> 6);   // partial-sum slot
     double* tile = red + (threadIdx.x >> 6) * kAnaTile;
