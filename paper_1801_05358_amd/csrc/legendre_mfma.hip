@@ -610,12 +610,11 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     auto coef_group = [&](int l, int slot) { cofb[slot][lane] = coef_fetch(cf, l, lmax, lane, 16); };
     double creg0 = 0.0;
 
-    // A operand of this lane: degree row, pair 4 (st % KH) + k; the mirror
-    // half reads (lam, q, p)
+    // A operand of this lane: degree row, pair 4 st + k (the north K step
+    // st and the mirror one st + KH share it)
     const int row = lane & 15;
     const int pofs = row * RL + k;
     const int oN[3] = {pofs, 16 * RL + pofs, 32 * RL + pofs};
-    const int oS[3] = {pofs, 32 * RL + pofs, 16 * RL + pofs};
     // eps of each output element: rounds advance by 16 degrees, so the
     // parity of a row is the same in every round
     T sg[4];
@@ -657,17 +656,21 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     auto round = [&](auto mode) {
         v4 CN[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
         v4 CS[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
+        // the north K step st and the mirror one st + KH read the same tile
+        // values (lam, p, q) of pair 4 st + k: one read each serves both,
+        // the mirror rows taking (lam, q, p)
 #pragma unroll
-        for (int st = 0; st < kAnaKS; ++st) {
-            const int* o = st < kAnaKH ? oN : oS;
-            const int po = 4 * (st % kAnaKH);
-#pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                v4& C = st < kAnaKH ? CN[f] : CS[f];
-                C = Mfma<T>::run(tl[o[f] + po], bop[st][f], C);
-            }
+        for (int st = 0; st < kAnaKH; ++st) {
+            const int po = 4 * st;
+            const T a0 = tl[oN[0] + po], a1 = tl[oN[1] + po], a2 = tl[oN[2] + po];
+            CN[0] = Mfma<T>::run(a0, bop[st][0], CN[0]);
+            CN[1] = Mfma<T>::run(a1, bop[st][1], CN[1]);
+            CN[2] = Mfma<T>::run(a2, bop[st][2], CN[2]);
+            CS[0] = Mfma<T>::run(a0, bop[st + kAnaKH][0], CS[0]);
+            CS[1] = Mfma<T>::run(a2, bop[st + kAnaKH][1], CS[1]);
+            CS[2] = Mfma<T>::run(a1, bop[st + kAnaKH][2], CS[2]);
             // keep the operand loads within a few K steps of their use
-            if (st % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            if (st % 2 == 1) __builtin_amdgcn_sched_barrier(0);
         }
         constexpr int kMode = decltype(mode)::value;
         if (kMode != 2 && wv == 0) {
