@@ -18,6 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
+# the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
+ABI_VERSION = 3
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -101,6 +103,8 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if L.dm_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {L.dm_abi_version()}, the binding needs {ABI_VERSION}: rebuild it")
     _lib = L
     return L
 
