@@ -1,0 +1,178 @@
+"""Configuration 4 at full size: Nside 512, lmax 1024, 64 right-hand sides
+in one call, on the FP64 and the FP32 (mixed) matrix-core paths.
+
+The oracle cannot transform 64 maps of this size in seconds, so every check
+takes outputs it can compute one by one, with synthetic inputs only:
+* batched synthesis of 64 signal realizations on sampled rings and batched
+  analysis of 64 noise realizations on sampled (l, m), for three RHS
+  (the first, one inside a column tile, the last);
+* one messenger iteration of 64 RHS (the launch configuration of the
+  solver): u = F^lambda A t on sampled (l, m);
+* constrained realizations (eq 19) of one data map and 63 fluctuation
+  inputs in one call, after one iteration at lambda = 1, where the solver's
+  result is F A (masked data) in closed form: s_CR and the fluctuation part
+  on sampled (l, m).
+FP64 matches to 1e-11 of the sampled values' scale (1e-11 plus the polar
+l^2 eps of the three-term recurrences on polar rings), mixed to 1e-5
+relative per field.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dm
+from oracle.geometry import healpix_grid, pixel_weights
+from oracle.sht import SHT, alm_index
+from paper_1801_05358_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CFG = 4
+NRHS = 64
+SAMPLE = (0, 37, 63)
+
+
+@pytest.fixture(scope="module")
+def dmwf():
+    from paper_1801_05358_amd import dmwf as mod
+    assert mod.device_count() > 0, "no GPU visible"
+    return mod
+
+
+@pytest.fixture(scope="module")
+def case():
+    """Inputs of configuration 4 and the oracle's sampled values, computed
+    once for both precisions."""
+    p = inputs.make_problem(CFG)
+    nside, lmax = p["nside"], p["lmax"]
+    grid = healpix_grid(nside)
+    sht = SHT(grid, lmax, cache_bytes=0)
+    print(f"config 4 inputs nside={nside} lmax={lmax} nrhs={NRHS}", flush=True)
+    alm = np.stack([inputs.signal_alm(CFG, lmax, k) for k in range(NRHS)])
+    maps = np.stack([inputs.noise_map(CFG, p["ncov"], p["obs"], k) for k in range(NRHS)])
+    nr = 4 * nside - 1
+    rings = [0, 1, 3 * nside // 4, nside - 2, nside - 1, nside, 2 * nside - 1, 3 * nside, nr - nside + 1, nr - 1]
+    rng = np.random.default_rng(512)
+    modes = [(0, 0), (2, 0), (3, 1), (100, 3), (lmax // 2, lmax // 2 - 1), (lmax, lmax), (lmax, 7),
+             (lmax - 1, lmax // 3)]
+    for _ in range(4):
+        l = int(rng.integers(2, lmax + 1))
+        modes.append((l, int(rng.integers(0, l + 1))))
+    w = pixel_weights(grid)[0]
+    ring_ref = {k: sht.synthesis(alm[k], rings=rings) for k in SAMPLE}
+    mode_ref = {k: sht.adjoint_modes(maps[k], modes) * w for k in SAMPLE}
+    print("config 4 oracle samples done", flush=True)
+    return dict(p=p, grid=grid, sht=sht, alm=alm, maps=maps, rings=rings, modes=modes, w=w,
+                ring_ref=ring_ref, mode_ref=mode_ref, cache={})
+
+
+def make_plan(dmwf, case, precision):
+    p = case["p"]
+    prec = dmwf.FP64 if precision == "fp64" else dmwf.MIXED
+    plan = dmwf.Plan(lmax=p["lmax"], nside=p["nside"], max_rhs=NRHS, precision=prec)
+    plan.set_spectra(p["cl"])
+    plan.set_noise(p["ncov"], p["obs"])
+    return plan
+
+
+def filter_modes(F, a, modes):
+    """F per (l, m) on sampled coefficients a [3, K]."""
+    FTT, FTE, FEE, FBB = F
+    ls = np.array([l for l, _ in modes])
+    return np.stack([FTT[ls] * a[0] + FTE[ls] * a[1], FTE[ls] * a[0] + FEE[ls] * a[1], FBB[ls] * a[2]])
+
+
+def pick(alm, modes, lmax):
+    return alm[:, [alm_index(l, m, lmax) for l, m in modes]]
+
+
+def check_modes(got, ref, precision, what, extra=None):
+    """Per field: FP64 max error within 1e-11 of the sampled scale (plus
+    the rounding of an exact FP64 term added to both), mixed relative L2
+    within 1e-5."""
+    for f in range(3):
+        err = got[f] - ref[f] if extra is None else (got[f] - extra[f]) - ref[f]
+        if precision == "fp64":
+            tol = 1e-11 * np.abs(ref[f]).max() + (0 if extra is None else 4e-16 * np.abs(extra[f]).max())
+            assert np.abs(err).max() <= tol, (what, f, np.abs(err).max(), tol)
+        else:
+            rel = np.linalg.norm(err) / np.linalg.norm(ref[f])
+            assert rel < 1e-5, (what, f, rel)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_transforms(dmwf, case, precision):
+    lmax, nside = case["p"]["lmax"], case["p"]["nside"]
+    grid = case["grid"]
+    print(f"config 4 batched transforms {precision}", flush=True)
+    plan = make_plan(dmwf, case, precision)
+    mp = plan.alm2map(case["alm"])
+    for k in SAMPLE:
+        got = np.concatenate([mp[k][:, grid["offset"][r]:grid["offset"][r] + grid["nphi"][r]] for r in case["rings"]], 1)
+        ref = np.concatenate(case["ring_ref"][k], 1)
+        if precision == "fp64":
+            for r, blk in zip(case["rings"], case["ring_ref"][k]):
+                o, n = grid["offset"][r], grid["nphi"][r]
+                err = np.abs(mp[k][:, o:o + n] - blk).max()
+                polar = r < nside or r >= 3 * nside
+                tol = (lmax ** 2 * 2.2e-16 * 4) if polar else 1e-11
+                assert err <= tol * np.abs(blk).max() + 1e-13, (k, r, err)
+        else:
+            for f in range(3):
+                rel = np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])
+                assert rel < 1e-5, (k, f, rel)
+    del mp
+    alm = plan.map2alm(case["maps"])
+    for k in SAMPLE:
+        check_modes(pick(alm[k], case["modes"], lmax), case["mode_ref"][k], precision, ("analysis", k))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_iteration(dmwf, case, precision):
+    """dm_iterate on 64 RHS: u = F^lambda A t for the given iterate t."""
+    p = case["p"]
+    lmax = p["lmax"]
+    print(f"config 4 one iteration {precision}", flush=True)
+    plan = make_plan(dmwf, case, precision)
+    lam = 37.0
+    t = case["maps"]
+    d = t[::-1]                                  # the data only enter t_out
+    u, _ = plan.iterate(d, t, lam, 1)
+    st = dm.setup(case["grid"], p["ncov"], p["obs"], d[0])
+    F = dm.messenger_filter(p["cl"], (lam - 1) * st["tau"], st["tau"])
+    for k in SAMPLE:
+        ref = filter_modes(F, case["mode_ref"][k], case["modes"])
+        check_modes(pick(u[k], case["modes"], lmax), ref, precision, ("iterate", k))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_constrained_realizations(dmwf, case, precision):
+    """One data map d and 63 fluctuation inputs (d_hat_k, s_hat_k); with one
+    iteration at lambda = 1 the solve of data x is F^0 A (x observed), so
+    s_CR,k = F^0 A obs(d - d_hat_k) + s_hat_k and the fluctuation part is
+    s_hat_k - F^0 A obs(d_hat_k)."""
+    p = case["p"]
+    lmax = p["lmax"]
+    sht, modes, w = case["sht"], case["modes"], case["w"]
+    print(f"config 4 constrained realizations {precision}", flush=True)
+    nreal = NRHS - 1
+    d = inputs.noise_map(CFG, p["ncov"], p["obs"], 1000)
+    dhat = case["maps"][:nreal]
+    shat = case["alm"][1:]
+    plan = make_plan(dmwf, case, precision)
+    plan.set_schedule(1e3, 1, 1)
+    scr, fl = plan.constrained_realizations(d, shat, dhat, want_f=True)
+    cache = case["cache"]
+    if "st" not in cache:
+        st = dm.setup(case["grid"], p["ncov"], p["obs"], d)
+        cache["st"] = st
+        cache["Ad"] = sht.adjoint_modes(st["d0"], modes) * w
+        cache["Ah"] = {k: sht.adjoint_modes(dhat[k] * st["obs"], modes) * w for k in (0, 37, nreal - 1)}
+    st = cache["st"]
+    F = dm.messenger_filter(p["cl"], 0.0 * st["tau"], st["tau"])
+    fd = filter_modes(F, cache["Ad"], modes)
+    for k, Ah in cache["Ah"].items():
+        fh = filter_modes(F, Ah, modes)
+        sh = pick(shat[k], modes, lmax)
+        check_modes(pick(scr[k], modes, lmax), fd - fh, precision, ("s_cr", k), extra=sh)
+        check_modes(pick(fl[k], modes, lmax), -fh, precision, ("fluctuation", k), extra=sh)
