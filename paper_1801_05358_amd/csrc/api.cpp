@@ -692,6 +692,16 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         REQUIRE(p->fft_lds_bytes <= 160 * 1024, DM_EUNSUPPORTED,
                 "ring length needs a transform buffer of " + std::to_string(lds_max) +
                     " points, beyond the LDS of one workgroup in double precision");
+        // Whole-ring workgroups: when one transform buffer takes more than
+        // half the LDS, a CU holds one workgroup, and 1024 threads (four
+        // waves per SIMD) hide more LDS latency than 512; otherwise two
+        // 512-thread workgroups fit.  DMWF_RING_THREADS overrides (256, 512
+        // or 1024).
+        p->ring_threads = p->fft_lds_bytes > 80 * 1024 ? 1024 : 512;
+        {
+            const int rt = env_int("DMWF_RING_THREADS", 0);
+            if (rt == 256 || rt == 512 || rt == 1024) p->ring_threads = rt;
+        }
         HIPCHK(hipStreamCreate(&p->stream));
         p->graphs = env_int("DMWF_GRAPHS", 1) != 0;
 

@@ -113,7 +113,8 @@ struct dm_plan {
     int mfma_mode = -1;                               // -1 auto, 0 off, 1 on (FP64 plans)
     int syn_threads = 128, syn_R = 1;
     int syn_mchunk = 4, ana_mchunk = 4;               // batched kernels: consecutive m per XCD chunk
-    int fft_threads = 512;
+    int fft_threads = 512;          // threads of a split-ring workgroup
+    int ring_threads = 512;         // threads of a whole-ring workgroup (<= 1024)
     // ring pairs of the unsplit and the split lengths (the split launch runs
     // only when some length is split)
     int n_whole = 0, n_split = 0;

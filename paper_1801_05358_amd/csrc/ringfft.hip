@@ -234,7 +234,7 @@ __device__ __forceinline__ C2<R> unit_root(int e, int n) {
 // checked when the plan is made); the other rings run in a launch of their
 // own, so that neither carries the other's registers or buffer size.
 template <int MODE, int SPLITK, typename R, typename P>
-__global__ __launch_bounds__(512) void ring_kernel(RingArgs<R> A, const double* __restrict__ map_in,
+__global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<R> A, const double* __restrict__ map_in,
                                                    double* __restrict__ map_out, const double* __restrict__ Kp,
                                                    const double* __restrict__ bp, C2<P>* __restrict__ phase) {
     typedef C2<R> CR;
@@ -541,11 +541,11 @@ template <int MODE, typename R, typename P>
 void launch_both(dm_plan* p, const RingArgs<R>& A, const double* map_in, double* map_out, const double* K,
                  const double* b, C2<P>* ph, hipStream_t s) {
     if (p->n_split == 0) {
-        launch_mode<MODE, 0, R, P>(A, p->npairs, nullptr, p->fft.lds_elems, p->fft_threads, map_in, map_out, K, b,
+        launch_mode<MODE, 0, R, P>(A, p->npairs, nullptr, p->fft.lds_elems, p->ring_threads, map_in, map_out, K, b,
                                    ph, s);
         return;
     }
-    launch_mode<MODE, 0, R, P>(A, p->n_whole, p->d_plist_whole, p->fft.lds_elems, p->fft_threads, map_in, map_out,
+    launch_mode<MODE, 0, R, P>(A, p->n_whole, p->d_plist_whole, p->fft.lds_elems, p->ring_threads, map_in, map_out,
                                K, b, ph, s);
     if (p->split_k <= 2)
         launch_mode<MODE, 2, R, P>(A, p->n_split, p->d_plist_split, p->fft.lds_split, p->fft_threads, map_in,
