@@ -26,6 +26,7 @@ Prints one JSON line.  Usage:
 import argparse
 import gc
 import csv
+import re
 import hashlib
 import json
 import os
@@ -90,10 +91,12 @@ def read_traffic(kernel, prec, nrhs):
     return float(rec["bytes_per_launch"])
 
 
-def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command):
+def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command, last):
     """Per-launch HBM bytes of the Legendre kernels from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
-    same counter reads for the calibration copy of COPY_BYTES."""
+    same counter reads for the calibration copy of COPY_BYTES.  Only each
+    kernel's last ``last`` dispatches count: the autotuner's candidate
+    launches come first and run other workgroup placements."""
     def per_kernel(path, counter):
         acc = {}
         for r in csv.DictReader(open(path)):
@@ -107,7 +110,7 @@ def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command):
     def find(acc, key):
         for name, d in acc.items():
             if key in name:
-                return sorted(d.values())
+                return [v for _, v in sorted(d.items(), key=lambda kv: int(kv[0]))][-last:]
         return []
 
     def copy_factor(path, counter):
@@ -138,6 +141,38 @@ def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command):
             out.write(f"write_bytes_per_launch: {wb:.6e}\n")
             out.write(f"bytes_per_launch: {fb + wb:.6e}\n")
         print(f"{kernel}: fetch {fb / 1e9:.3f} GB, write {wb / 1e9:.3f} GB per launch")
+
+
+def kernel_summary(stats_csv, trace_csv, out, command, title, last):
+    """Kernel-time summary of a rocprofv3 --kernel-trace --stats run: the
+    profiler's own statistics over every dispatch (the autotuner's candidate
+    launches included), then, from the trace, each kernel's average over its
+    last ``last`` dispatches (the run whose HIP-event times the bench reports)."""
+    def short(n):
+        n = re.sub(r"dmwf::\(anonymous namespace\)::", "", n)
+        return re.sub(r"\(.*$", "", n)[:60]
+    lines = [f"# {title}", f"# command: {command}", "# rocprofv3 kernel statistics over all dispatches (microseconds)",
+             f"{'kernel':60s} {'calls':>6s} {'avg_us':>12s} {'min_us':>12s} {'max_us':>12s} {'pct':>7s}"]
+    for r in csv.DictReader(open(stats_csv)):
+        if float(r["Percentage"]) < 0.01:
+            continue
+        lines.append(f"{short(r['Name']):60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:12.1f} "
+                     f"{float(r['MinNs']) / 1e3:12.1f} {float(r['MaxNs']) / 1e3:12.1f} {float(r['Percentage']):7.2f}")
+    per = {}
+    for r in csv.DictReader(open(trace_csv)):
+        per.setdefault(short(r["Kernel_Name"]), []).append(
+            (int(r["Dispatch_Id"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    lines += ["", f"# from the kernel trace: average over each kernel's last {last} dispatches (microseconds)",
+              f"{'kernel':60s} {'n':>6s} {'avg_us':>12s}"]
+    rows = []
+    for k, v in per.items():
+        d = [t for _, t in sorted(v)][-last:]
+        rows.append((sum(d) / len(d), k, len(d)))
+    for avg, k, n in sorted(rows, reverse=True):
+        if avg >= 50.0:
+            lines.append(f"{k:60s} {n:6d} {avg:12.1f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(lmax, nside, alm):
@@ -207,9 +242,20 @@ def main():
                     help="end with one device copy of 1 GiB (scale for the traffic counters)")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--traffic-command", default="")
+    ap.add_argument("--traffic-last", type=int, default=6,
+                    help="dispatches per kernel that count (the timed and the profiled run of --steps 3)")
+    ap.add_argument("--kernel-summary", nargs=3, metavar=("STATS_CSV", "TRACE_CSV", "OUT"),
+                    help="write a kernel-time summary from a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--summary-title", default="")
+    ap.add_argument("--summary-last", type=int, default=20,
+                    help="dispatches per kernel averaged from the trace (the profiled run of --steps 20)")
     args = ap.parse_args()
     if args.traffic:
-        traffic_from_csv(args.traffic[0], args.traffic[1], args.precision, args.nrhs, args.traffic_command)
+        traffic_from_csv(args.traffic[0], args.traffic[1], args.precision, args.nrhs, args.traffic_command,
+                         args.traffic_last)
+        return
+    if args.kernel_summary:
+        kernel_summary(*args.kernel_summary, args.traffic_command, args.summary_title, args.summary_last)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); how the path would shard "
