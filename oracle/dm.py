@@ -29,7 +29,10 @@ Follows the paper step by step (Kodi Ramanah, Lavaux & Wandelt 2018):
 * diagnostics: the Cauchy ratio of Algorithm 1's stopping rule, the residual
   ||A x - y|| / ||y|| with A = 1 + S^1/2 N^-1 S^1/2 (Appendix C; here
   x = S^-1/2 u, y = S^1/2 Y^T N^-1 d) and the chi^2 of eq 3;
-* constrained realizations, eq 19: s_CR = W(d - d_hat) + s_hat.
+* constrained realizations, eq 19: s_CR = W(d - d_hat) + s_hat;
+* Appendix A's refinement (modified Jacobi relaxation), in the form that
+  carries over to the sphere: corrections s += W~(W Y r) with r the
+  residual of the Wiener filter equation on the range of S (refine()).
 """
 
 import numpy as np
@@ -169,10 +172,17 @@ def schedule(lambda0, nsteps):
 def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False):
     """Run the dual messenger loop.  Returns dict(u [3, nalm], ux = Y u
     [3, npix], tau, cauchy (last), trace (list of per-iteration cauchy))."""
-    lmax = sht.lmax
     st = setup(sht.grid, ncov, obs, d)
-    tau, K, b = st["tau"], st["K"], st["b"]
-    t = st["d0"].copy()
+    u, ux, cauchy = messenger_run(sht, st["d0"], st["K"], st["b"], st["tau"], cl, lambda0, nsteps, iters_per_step)
+    return dict(u=u, ux=ux, tau=st["tau"], cauchy=cauchy[-1] if cauchy else float("nan"),
+                trace=cauchy if trace else None, setup=st)
+
+
+def messenger_run(sht, t, K, b, tau, cl, lambda0, nsteps, iters_per_step):
+    """Algorithm 1's loop under the fixed schedule from the messenger t,
+    with the pixel update t = K u_x + b.  Returns (u, u_x = Y u, the
+    per-iteration Cauchy ratios)."""
+    lmax = sht.lmax
     u_prev = None
     cauchy = []
     u = ux = None
@@ -187,8 +197,7 @@ def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False):
             if u_prev is not None:
                 cauchy.append(cauchy_ratio(u, u_prev, lmax))
             u_prev = u
-    return dict(u=u, ux=ux, tau=tau, cauchy=cauchy[-1] if cauchy else float("nan"),
-                trace=cauchy if trace else None, setup=st)
+    return u, ux, cauchy
 
 
 def eps_schedule(lambda0, beta):
@@ -285,6 +294,68 @@ def cauchy_ratio(u, u_prev, lmax):
     num = sum(alm_dot(u[f] - u_prev[f], u[f] - u_prev[f], lmax) for f in range(3))
     den = sum(alm_dot(u[f], u[f], lmax) for f in range(3))
     return float(np.sqrt(num / den)) if den > 0 else 0.0
+
+
+# ----------------------------------------------------------------------------
+# refinement by the modified Jacobi relaxation (Appendix A)
+# ----------------------------------------------------------------------------
+def prior_pinv(cl):
+    """S^+ per l: the pseudo-inverse of the TE block and of BB (zero where
+    the spectrum is zero)."""
+    return matrix_function(cl, lambda s: np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0))
+
+
+def prior_range(cl):
+    """Pi per l: the orthogonal projector onto the range of S_l."""
+    return matrix_function(cl, lambda s: (s > 0).astype(float))
+
+
+def wf_residual(sht, s, st, cl):
+    """r = Pi Y^T P (d0 - Y s) - S^+ s, the residual of the Wiener filter
+    equation (S^+ + Pi Y^T P Y) s = Pi Y^T P d on the range of S (eq 2 in
+    the form (1 + S Y^T P Y) s = S Y^T P d, multiplied by S^+)."""
+    lmax = sht.lmax
+    e = sht.adjoint(pix_apply(st["ninv"], st["d0"] - sht.synthesis(s)))
+    return apply_blocks(prior_range(cl), e, lmax) - apply_blocks(prior_pinv(cl), s, lmax)
+
+
+def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
+    """Appendix A's relaxation on the sphere: s_0 = W~ d (the fixed-schedule
+    messenger run of solve()), then ncorr corrections
+        s_{n+1} = s_n + W~(g_n),  g_n = W Y r_n,  r_n = wf_residual(s_n),
+    where W~(g) is the same messenger run (schedule and counts) driven by
+    weighted data g in place of P d, b = T_p g, from t_0 = 0: one linear
+    operator for every correction.  (Started from P^+ g, the pseudo-inverse
+    image that t_0 = d0 is for g = P d, a short run's transient overshoots
+    where N_p has large eigenvalues, and the corrections diverge with
+    correlated noise.)
+    W Y is a right inverse of the adjoint Y^T where the quadrature is exact,
+    so g_n stands for the data whose Wiener filter is A^-1 r_n; the paper's
+    flat-sky form (data minus W^+ s_n) needs a square, unitary basis change.
+    The fixed point has r = 0 whenever Y^T W Y is invertible, whatever the
+    grid and W~.  Returns dict(u, history = ||r_n|| / ||Pi Y^T P d0|| before each
+    correction and after the last)."""
+    lmax = sht.lmax
+    st = setup(sht.grid, ncov, obs, d)
+    tau, K = st["tau"], st["K"]
+    w = pixel_weights(sht.grid)
+    Tp = tau / w
+    y = apply_blocks(prior_range(cl), sht.adjoint(pix_apply(st["ninv"], st["d0"])), lmax)
+    ny = np.sqrt(sum(alm_dot(y[f], y[f], lmax) for f in range(3)))
+
+    def rel_norm(r):
+        return float(np.sqrt(sum(alm_dot(r[f], r[f], lmax) for f in range(3))) / ny)
+
+    s = messenger_run(sht, st["d0"], K, st["b"], tau, cl, lambda0, nsteps, iters)[0]
+    hist = []
+    for _ in range(ncorr):
+        r = wf_residual(sht, s, st, cl)
+        hist.append(rel_norm(r))
+        g = w * sht.synthesis(r)
+        delta = messenger_run(sht, np.zeros_like(g), K, Tp * g, tau, cl, lambda0, nsteps, iters)[0]
+        s = s + delta
+    hist.append(rel_norm(wf_residual(sht, s, st, cl)))
+    return dict(u=s, history=hist)
 
 
 # ----------------------------------------------------------------------------
