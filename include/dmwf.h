@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 3
+#define DMWF_ABI_VERSION 4
 
 typedef enum {
     DM_OK = 0,
@@ -194,6 +194,43 @@ dm_status dm_set_schedule(dm_plan* plan, const dm_schedule* schedule);
  * the iteration count; *n = 0 after a fixed-mode solve.  Errors: DM_EINVAL
  * for a null plan or n.                                                    */
 dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int cap, int* n);
+
+/* Refinement by Appendix A's modified Jacobi relaxation: every later
+ * Wiener filter solve (also inside dm_constrained_realizations) follows
+ * its messenger run with ncorrections corrections
+ *     s <- s + W~(g),  g = W Y r,  r = Pi Y^T P (d - Y s) - S^+ s,
+ * r the residual of the Wiener filter equation on the range of S (eq 2;
+ * Pi the projector onto it, S^+ the pseudo-inverse, P as for
+ * dm_set_noise_masks), evaluated with FP64 transforms in either precision,
+ * and W~ the same fixed-schedule messenger run driven by the weighted
+ * data g (b = T_p g) from t = 0.  W Y, the pixel weights times synthesis,
+ * is a right inverse of the adjoint Y^T where the quadrature is exact; it
+ * takes the place of the paper's flat-sky d - W^+ s (eq A1), and the fixed
+ * point solves the Wiener filter equation exactly on any grid on which
+ * Y^T W Y is invertible, so the corrections also remove the messenger's
+ * own HEALPix quadrature bias and, on a DM_MIXED plan, the FP32 rounding.
+ * Each correction costs one messenger run plus five FP64 transforms.  The
+ * corrections converge when W~ approximates the inverse well enough (the
+ * residual norm falls by a factor of about 3 per correction on HEALPix
+ * with diagonal noise); with correlated noise on HEALPix a long schedule
+ * can make them grow, which dm_refinement_trace shows.
+ * ncorrections in [0, 1000], 0 = off (the default), else DM_EINVAL;
+ * allocates a map and an alm buffer for max_rhs right-hand sides when
+ * first enabled (DM_ENOMEM).  A refined solve needs the fixed schedule
+ * without an iteration cap and no pending checkpoint (else
+ * DM_EUNSUPPORTED from the solve), leaves nothing for
+ * dm_checkpoint_save, and reports in dm_stats the iterations of all runs,
+ * and as `cauchy` the last correction's relative size.                    */
+dm_status dm_set_refinement(dm_plan* plan, int ncorrections);
+
+/* Residual history of the last refined solve: history[k * nrhs + r] =
+ * ||r_k|| / ||Pi Y^T P d|| for right-hand side r before correction k
+ * (k = 0 .. ncorrections - 1) and after the last (k = ncorrections), the
+ * norms harmonic L2 with m > 0 counted twice.  Copies min(cap, n) values
+ * to the caller's host array (NULL allowed), sets *n = (ncorrections + 1)
+ * nrhs and *nrhs (NULL allowed) to that solve's nrhs; both 0 before any
+ * refined solve.  Errors: DM_EINVAL for a null plan or n.                 */
+dm_status dm_refinement_trace(const dm_plan* plan, double* history, int cap, int* n, int* nrhs);
 
 /* Wiener filter of nrhs data maps d [nrhs][3][npix] (Algorithm 1).  Writes
  * the final iterate u (the Wiener-filtered T, E, B alm) to alm

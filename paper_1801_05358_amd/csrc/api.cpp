@@ -363,12 +363,115 @@ bool same_schedule(const dm_schedule& a, const dm_schedule& b) {
 //   map: nullable device [nrhs][3][npix] (receives Y u).
 // resumable: a Wiener filter solve, which continues a loaded checkpoint
 // and leaves its own state for dm_checkpoint_save.
+// Iterations [from, end) of the fixed schedule on the iterate alm, from the
+// ring Fourier data of the current messenger t; the solve's last iteration
+// keeps the previous iterate in d_alm_prev and ends with u_x = Y u in d_ux.
+void fixed_loop(dm_plan* p, int nrhs, double* alm, int64_t from, int64_t end, hipStream_t s, StepGraphs& graphs) {
+    const size_t per = (size_t)(p->lmax + 1) * 4;
+    const int niter = p->sched.iters_per_step;
+    const size_t alm_bytes = (size_t)nrhs * 3 * p->nalm * 2 * sizeof(double);
+    for (int64_t it = from; it < end;) {
+        const int64_t k = it / niter;
+        const double* F = p->d_filters + per * k;
+        // this cooling step's iterations before the solve's last one
+        const int64_t stop = std::min<int64_t>((k + 1) * niter, end - 1);
+        if (it < stop) {
+            run_iterations(p, nrhs, F, alm, (int)(stop - it), s, graphs);
+            it = stop;
+            continue;
+        }
+        // the last iteration: keep the previous iterate (final Cauchy
+        // ratio) and end with u_x = Y u
+        HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
+        leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
+        leg_synthesis(p, nrhs, p->d_alm_spin, s);
+        ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+        ++it;
+    }
+}
+
+// Appendix A's refinement (a modified Jacobi relaxation), on the sphere:
+// with W~ the fixed-schedule messenger run, p->refine corrections
+//   s <- s + W~(g),  g = W Y r,  r = Pi Y^T P (d0 - Y s) - S^+ s,
+// r the residual of the Wiener filter equation on the range of S (FP64
+// transforms, whatever the plan's precision) and W Y a right inverse of the
+// adjoint Y^T where the quadrature is exact.  W~(g) runs the same schedule
+// from t = 0 with b = T_p g = -tau Y r~ (r~ = -r), so that every correction
+// applies one linear operator, and its fixed point solves the Wiener filter
+// equation exactly.  Records ||r|| / ||Pi Y^T P d0|| before each correction
+// and after the last in p->refine_hist.
+void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, hipStream_t s) {
+    const int64_t na2 = (int64_t)nrhs * 3 * p->nalm * 2;
+    const int64_t nmap = (int64_t)nrhs * 3 * p->npix;
+    const size_t alm_bytes = (size_t)na2 * sizeof(double);
+    const int nb = alm_norm_blocks(p);
+    double* parts = p->d_red + 64 + (int64_t)nrhs * p->nrings;
+    std::vector<double> hparts((size_t)nrhs * nb * 2), ynorm(nrhs, 0.0);
+    p->refine_hist.assign((size_t)(p->refine + 1) * nrhs, 0.0);
+    p->refine_nrhs = nrhs;
+    // r~ = -r into d_alm_r, its relative norm into refine_hist[k]
+    auto residual = [&](int k) {
+        PrecisionScope fp64(p, DM_FP64);
+        alm2map_dev(p, nrhs, alm, p->d_ux, s);
+        // d_ux <- P (Y s - d0); d_b2 <- P d0 (used at k = 0)
+        HIPCHK(launch_residual_maps(p, nrhs, p->d_ux, p->d_d0, p->d_b2, p->d_red + 64, s));
+        map2alm_dev(p, nrhs, p->d_ux, p->d_alm_r, false, s);
+        if (k == 0) map2alm_dev(p, nrhs, p->d_b2, p->d_alm_y, false, s);
+        HIPCHK(launch_refine_residual(p, nrhs, p->d_alm_r, alm, k == 0 ? p->d_alm_y : nullptr, parts, s));
+        HIPCHK(hipMemcpyAsync(hparts.data(), parts, hparts.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int r = 0; r < nrhs; ++r) {
+            double q0 = 0.0, q1 = 0.0;
+            for (int b = 0; b < nb; ++b) {
+                q0 += hparts[((size_t)r * nb + b) * 2];
+                q1 += hparts[((size_t)r * nb + b) * 2 + 1];
+            }
+            if (k == 0) ynorm[r] = std::sqrt(q1);
+            p->refine_hist[(size_t)k * nrhs + r] = ynorm[r] > 0.0 ? std::sqrt(q0) / ynorm[r] : 0.0;
+        }
+    };
+    for (int n = 0; n < p->refine; ++n) {
+        residual(n);
+        {
+            PrecisionScope fp64(p, DM_FP64);
+            alm2map_dev(p, nrhs, p->d_alm_r, p->d_ux, s);
+        }
+        HIPCHK(launch_scale(p->d_b2, p->d_ux, -p->tau, nmap, s));
+        // W~(g): the schedule from t = 0, with b = d_b2 in place of the data's
+        std::swap(p->d_b, p->d_b2);
+        try {
+            HIPCHK(hipMemsetAsync(p->d_ux, 0, (size_t)nmap * sizeof(double), s));
+            ring(p, RING_ANALYSIS, nrhs, p->d_ux, nullptr, nullptr, s);
+            HIPCHK(hipMemsetAsync(p->d_alm_corr, 0, alm_bytes, s));
+            StepGraphs graphs(s);
+            fixed_loop(p, nrhs, p->d_alm_corr, 0, full, s, graphs);
+        } catch (...) {
+            std::swap(p->d_b, p->d_b2);
+            throw;
+        }
+        std::swap(p->d_b, p->d_b2);
+        // the iterate before the last correction, for the final Cauchy ratio
+        if (n == p->refine - 1) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_axpby(alm, p->d_alm_corr, 1.0, 1.0, na2, s));
+    }
+    residual(p->refine);
+}
+
 void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, hipStream_t s, dm_stats* stats,
                bool resumable) {
     REQUIRE(p->noise_set, DM_ESTATE, "dm_set_noise must be called before solving");
     REQUIRE(p->spectra_set, DM_ESTATE, "dm_set_spectra must be called before solving");
     check_rhs(p, nrhs);
     const auto t0 = std::chrono::steady_clock::now();
+    if (p->refine > 0) {
+        REQUIRE(!eps_mode(p->sched), DM_EUNSUPPORTED,
+                "refinement needs the fixed schedule (every correction applies the same operator)");
+        REQUIRE(p->sched.max_iters <= 0, DM_EUNSUPPORTED, "refinement does not combine with an iteration cap");
+        REQUIRE(!p->resume.pending, DM_EUNSUPPORTED, "refinement does not resume from a checkpoint");
+        // a refined solve leaves nothing to checkpoint
+        p->state.valid = false;
+        resumable = false;
+    }
     const std::vector<double> lam = schedule_lambdas(p->sched);
     prepare_filters(p, lam);
     sync_plan_stream_to(p, s);
@@ -424,26 +527,13 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         const int64_t full = (int64_t)nsteps * niter;
         const int64_t end = p->sched.max_iters > 0 ? std::min<int64_t>(full, p->sched.max_iters) : full;
         if (rs) restart_from_u(total >= end);
-        for (int64_t it = total; it < end;) {
-            const int64_t k = it / niter;
-            const double* F = p->d_filters + per * k;
-            // this cooling step's iterations before the solve's last one
-            const int64_t stop = std::min<int64_t>((k + 1) * niter, end - 1);
-            if (it < stop) {
-                run_iterations(p, nrhs, F, alm, (int)(stop - it), s, graphs);
-                it = stop;
-                continue;
-            }
-            // the last iteration: keep the previous iterate (final Cauchy
-            // ratio) and end with u_x = Y u
-            HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
-            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
-            leg_synthesis(p, nrhs, p->d_alm_spin, s);
-            ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
-            ++it;
-        }
+        fixed_loop(p, nrhs, alm, total, end, s, graphs);
         total = std::max(total, end);
         finished = total >= full;
+        if (p->refine > 0) {
+            refine_dev(p, nrhs, alm, full, s);
+            total *= 1 + p->refine;
+        }
     } else {
         // Algorithm 1's loop: per cooling step, repeat until the Cauchy ratio
         // (largest over the RHS) is below that step's threshold.  The ratio
@@ -523,7 +613,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     // epilogue in FP64 (section a8): a mixed plan recomputes s_x = Y u with
     // the FP64 transforms before it is returned or enters the residual
     std::unique_ptr<PrecisionScope> fp64;
-    if (p->precision == DM_MIXED && (map || stats)) {
+    if ((p->precision == DM_MIXED || (p->refine > 0 && !eps)) && (map || stats)) {
         fp64.reset(new PrecisionScope(p, DM_FP64));
         alm2map_dev(p, nrhs, alm, p->d_ux, s);
     }
@@ -589,6 +679,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
     dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
+    dfree(p->d_b2); dfree(p->d_alm_corr);
     dfree(p->d_cpart); dfree(p->d_cout);
     if (p->h_cout) (void)hipHostFree(p->h_cout);
     if (p->h_pinned) (void)hipHostFree(p->h_pinned);
@@ -1215,6 +1306,27 @@ dm_status dm_checkpoint_load(dm_plan* p, const char* path) {
         rs.pending = true;
         p->resume = std::move(rs);
     });
+}
+
+dm_status dm_set_refinement(dm_plan* p, int ncorrections) {
+    return guarded(p, [&] {
+        REQUIRE(ncorrections >= 0 && ncorrections <= 1000, DM_EINVAL, "ncorrections must be in [0, 1000]");
+        if (ncorrections > 0 && !p->d_b2) {
+            dalloc(p, p->d_b2, (size_t)p->max_rhs * 3 * p->npix);
+            dalloc(p, p->d_alm_corr, (size_t)p->max_rhs * 3 * p->nalm * 2);
+        }
+        p->refine = ncorrections;
+    });
+}
+
+dm_status dm_refinement_trace(const dm_plan* p, double* history, int cap, int* n, int* nrhs) {
+    if (!p || !n) return DM_EINVAL;
+    const int cnt = (int)p->refine_hist.size();
+    const int k = std::max(0, std::min(cap, cnt));
+    if (history) std::copy(p->refine_hist.begin(), p->refine_hist.begin() + k, history);
+    *n = cnt;
+    if (nrhs) *nrhs = cnt ? p->refine_nrhs : 0;
+    return DM_OK;
 }
 
 dm_status dm_schedule_trace(const dm_plan* p, double* cauchy, int* step, int cap, int* n) {

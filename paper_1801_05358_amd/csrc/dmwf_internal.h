@@ -168,6 +168,14 @@ struct dm_plan {
     double* h_cout = nullptr;          // pinned [max_rhs][2]
     std::vector<double> trace_cauchy;
     std::vector<int> trace_step;
+    // refinement (Appendix A): corrections per solve, the correction's own
+    // b and iterate (allocated when first enabled), and the relative
+    // residual norms of the last solve, [ncorr + 1][nrhs]
+    int refine = 0;
+    double* d_b2 = nullptr;            // [B][3][npix]
+    double* d_alm_corr = nullptr;      // [B][3][nalm] complex
+    std::vector<double> refine_hist;
+    int refine_nrhs = 0;
 
     // input fingerprints (checked when a solve resumes from a checkpoint)
     uint64_t hash_cl = 0, hash_noise = 0;
@@ -281,5 +289,11 @@ hipError_t launch_alm_norms(dm_plan* p, int nrhs, const double* u, const double*
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* count, hipStream_t s);
 // y = a * x + c * y  (elementwise)
 hipError_t launch_axpby(double* y, const double* x, double a, double c, int64_t n, hipStream_t s);
+// refinement residual per (l, m): e <- Pi e + S^+ u in place; parts [blocks][2]
+// = (|e|^2, |Pi y|^2) per block, blocks as alm_norm_blocks (y nullable)
+hipError_t launch_refine_residual(dm_plan* p, int nrhs, double* e, const double* u, const double* y, double* parts,
+                                  hipStream_t s);
+// y = a x
+hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);
 
 }  // namespace dmwf

@@ -362,6 +362,65 @@ __global__ void norm_kernel(int lmax, int64_t nalm, const double2* __restrict__ 
     }
 }
 
+// Refinement residual (Appendix A) per (l, m), grid (lblocks, mmax+1, nrhs):
+//   e <- Pi e + S^+ s   in place, with e = Y^T P (Y s - d0) on entry, so
+//   that e = -r, r the residual of the Wiener filter equation on the range
+//   of S;  Pi = S^+1/2 S^1/2 the projector onto that range.
+//   parts[blk][0] = sum |e|^2,  parts[blk][1] = sum |Pi y|^2 (y nullable),
+//   with weight 1 (m = 0) or 2 (m > 0).
+__global__ void refine_resid_kernel(int lmax, int64_t nalm, double2* __restrict__ e, const double2* __restrict__ u,
+                                    const double2* __restrict__ y, const double* __restrict__ mats,
+                                    double* __restrict__ parts) {
+    __shared__ double sh[kBlk];
+    const int m = blockIdx.y, rhs = blockIdx.z;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    double q0 = 0.0, q1 = 0.0;
+    if (l <= lmax) {
+        const int64_t idx = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
+        const double wt = m == 0 ? 1.0 : 2.0;
+        const double* sq = mats;                         // S^1/2
+        const double* isq = mats + 4 * (lmax + 1);       // S^+1/2
+        const double* inv = mats + 8 * (lmax + 1);       // S^+
+        // Pi = S^+1/2 S^1/2 (both functions of S_l, so the product is symmetric)
+        const double at = isq[4 * l], ab = isq[4 * l + 1], ae = isq[4 * l + 2];
+        const double bt = sq[4 * l], bb = sq[4 * l + 1], be = sq[4 * l + 2];
+        const double ptt = at * bt + ab * bb, pte = at * bb + ab * be, pee = ab * bb + ae * be;
+        const double pbb = isq[4 * l + 3] * sq[4 * l + 3];
+        const double itt = inv[4 * l], ite = inv[4 * l + 1], iee = inv[4 * l + 2], ibb = inv[4 * l + 3];
+        double2 ee[3], uu[3], yy[3];
+        for (int f = 0; f < 3; ++f) {
+            const int64_t k = ((int64_t)rhs * 3 + f) * nalm + idx;
+            ee[f] = e[k];
+            uu[f] = u[k];
+            yy[f] = y ? y[k] : make_double2(0.0, 0.0);
+        }
+        double2 o[3], py[3];
+        o[0] = make_double2(ptt * ee[0].x + pte * ee[1].x + itt * uu[0].x + ite * uu[1].x,
+                            ptt * ee[0].y + pte * ee[1].y + itt * uu[0].y + ite * uu[1].y);
+        o[1] = make_double2(pte * ee[0].x + pee * ee[1].x + ite * uu[0].x + iee * uu[1].x,
+                            pte * ee[0].y + pee * ee[1].y + ite * uu[0].y + iee * uu[1].y);
+        o[2] = make_double2(pbb * ee[2].x + ibb * uu[2].x, pbb * ee[2].y + ibb * uu[2].y);
+        py[0] = make_double2(ptt * yy[0].x + pte * yy[1].x, ptt * yy[0].y + pte * yy[1].y);
+        py[1] = make_double2(pte * yy[0].x + pee * yy[1].x, pte * yy[0].y + pee * yy[1].y);
+        py[2] = make_double2(pbb * yy[2].x, pbb * yy[2].y);
+        for (int f = 0; f < 3; ++f) {
+            e[((int64_t)rhs * 3 + f) * nalm + idx] = o[f];
+            q0 += wt * (o[f].x * o[f].x + o[f].y * o[f].y);
+            q1 += wt * (py[f].x * py[f].x + py[f].y * py[f].y);
+        }
+    }
+    const int64_t blk = ((int64_t)rhs * gridDim.y + m) * gridDim.x + blockIdx.x;
+    const double s0 = block_sum(q0, sh);
+    if (threadIdx.x == 0) parts[blk * 2] = s0;
+    const double s1 = block_sum(q1, sh);
+    if (threadIdx.x == 0) parts[blk * 2 + 1] = s1;
+}
+
+__global__ void scale_kernel(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i];
+}
+
 __global__ void count_nonfinite_kernel(const double* __restrict__ x, int64_t n, int* count) {
     int c = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -486,6 +545,20 @@ hipError_t launch_alm_norms(dm_plan* p, int nrhs, const double* u, const double*
     hipLaunchKernelGGL(norm_kernel, grid, dim3(kBlk), 0, s, p->lmax, p->nalm, reinterpret_cast<const double2*>(u),
                        reinterpret_cast<const double2*>(uprev), reinterpret_cast<const double2*>(r1),
                        reinterpret_cast<const double2*>(y1), mats, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_residual(dm_plan* p, int nrhs, double* e, const double* u, const double* y, double* parts,
+                                  hipStream_t s) {
+    dim3 grid(((p->lmax + 1) + kBlk - 1) / kBlk, p->mmax + 1, nrhs);
+    hipLaunchKernelGGL(refine_resid_kernel, grid, dim3(kBlk), 0, s, p->lmax, p->nalm, reinterpret_cast<double2*>(e),
+                       reinterpret_cast<const double2*>(u), reinterpret_cast<const double2*>(y), p->d_mats, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(kBlk), 0, s, y, x, a, n);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 # the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -81,6 +81,9 @@ def lib():
         "dm_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(DmSchedule)]),
         "dm_schedule_trace": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_int)]),
+        "dm_set_refinement": (ctypes.c_int, [_P, ctypes.c_int]),
+        "dm_refinement_trace": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int)]),
         "dm_wiener_filter": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, ctypes.POINTER(DmStats)]),
         "dm_wiener_filter_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
         "dm_constrained_realizations": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, _D, _D]),
@@ -112,7 +115,8 @@ def lib():
 def exported_symbols():
     """Names declared in include/dmwf.h that the binding expects."""
     return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
-            "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_wiener_filter",
+            "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_set_refinement",
+            "dm_refinement_trace", "dm_wiener_filter",
             "dm_wiener_filter_device",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
             "dm_map2alm_device", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
@@ -236,6 +240,20 @@ class Plan:
     def checkpoint_load(self, path):
         """Load a checkpoint; the next Wiener filter call continues from it."""
         self._check(lib().dm_checkpoint_load(self._h, os.fsencode(path)))
+
+    def set_refinement(self, ncorrections):
+        """Appendix A's corrections after every later solve (0 = off)."""
+        self._check(lib().dm_set_refinement(self._h, int(ncorrections)))
+
+    def refinement_trace(self):
+        """Relative residual norms of the last refined solve, [ncorr + 1, nrhs]
+        (before each correction and after the last)."""
+        n, b = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(lib().dm_refinement_trace(self._h, None, 0, ctypes.byref(n), ctypes.byref(b)))
+        h = np.zeros(n.value)
+        self._check(lib().dm_refinement_trace(self._h, h.ctypes.data_as(_D), n.value, ctypes.byref(n),
+                                              ctypes.byref(b)))
+        return h.reshape(-1, b.value) if n.value else h.reshape(0, 0)
 
     def schedule_trace(self):
         """(cauchy [n], step [n]) of the last epsilon-mode solve."""
