@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--noise", choices=["diag", "corr"], default="diag",
                     help="diag: diagonal noise, one mask; corr: correlated 3x3 noise with distinct T and P masks")
+    ap.add_argument("--refine", type=int, default=0,
+                    help="also run one solve with this many Appendix A corrections and report its residuals")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 reference solve and baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -382,6 +384,25 @@ def main():
         "ring_fft_hbm": {"achieved": round(rb / (ring_ms / max(ring_n, 1) * 1e-3) / 1e9, 1), "peak": HBM_PEAK,
                          "unit": "GB/s"},
     }
+
+    if args.refine > 0:
+        # Appendix A's corrections on the same batch and schedule (reported
+        # beside the line; `value` is the plain solve's rate)
+        log(f"[bench] refined solve, {args.refine} corrections")
+        set_iters(plan, args.steps)
+        plan.set_refinement(args.refine)
+        ref_out = torch.empty_like(out_t)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.wiener_filter_device(d_t, ref_out, stream=stream)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t1
+        h = plan.refinement_trace()
+        rec["refinement"] = {"corrections": args.refine, "iterations_per_run": args.steps, "seconds": round(tr, 3),
+                             "wf_residual_max_over_rhs": [float(f"{v:.3e}") for v in h.max(axis=1)],
+                             "note": "relative Wiener filter residual before each correction and after the last"}
+        plan.set_refinement(0)
+        del ref_out
 
     # the timed plan's device memory goes back before the reference plans
     # are made (at Nside 2048 two 8-RHS plans do not fit together)

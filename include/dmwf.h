@@ -209,18 +209,19 @@ dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int 
  * point solves the Wiener filter equation exactly on any grid on which
  * Y^T W Y is invertible, so the corrections also remove the messenger's
  * own HEALPix quadrature bias and, on a DM_MIXED plan, the FP32 rounding.
- * Each correction costs one messenger run plus five FP64 transforms.  The
- * corrections converge when W~ approximates the inverse well enough (the
- * residual norm falls by a factor of about 3 per correction on HEALPix
- * with diagonal noise); with correlated noise on HEALPix a long schedule
- * can make them grow, which dm_refinement_trace shows.
+ * Each correction costs one messenger run plus three FP64 transforms.  The
+ * corrections converge only where W~ approximates the inverse well enough
+ * (on Gauss-Legendre grids; on HEALPix with a moderate noise range and
+ * mask); elsewhere they stall or grow, which dm_refinement_trace shows, so
+ * each right-hand side returns the iterate of smallest residual norm seen
+ * (the first of equal ones): never worse than the plain solve.
  * ncorrections in [0, 1000], 0 = off (the default), else DM_EINVAL;
  * allocates a map and an alm buffer for max_rhs right-hand sides when
  * first enabled (DM_ENOMEM).  A refined solve needs the fixed schedule
  * without an iteration cap and no pending checkpoint (else
  * DM_EUNSUPPORTED from the solve), leaves nothing for
- * dm_checkpoint_save, and reports in dm_stats the iterations of all runs,
- * and as `cauchy` the last correction's relative size.                    */
+ * dm_checkpoint_save, and reports in dm_stats the iterations of all runs
+ * and `cauchy` = 0 (the residual history is the convergence record).      */
 dm_status dm_set_refinement(dm_plan* plan, int ncorrections);
 
 /* Residual history of the last refined solve: history[k * nrhs + r] =

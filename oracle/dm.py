@@ -333,8 +333,11 @@ def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
     so g_n stands for the data whose Wiener filter is A^-1 r_n; the paper's
     flat-sky form (data minus W^+ s_n) needs a square, unitary basis change.
     The fixed point has r = 0 whenever Y^T W Y is invertible, whatever the
-    grid and W~.  Returns dict(u, history = ||r_n|| / ||Pi Y^T P d0|| before each
-    correction and after the last)."""
+    grid and W~.  The corrections converge only where W~ is close enough to
+    the inverse; the result is the iterate with the smallest residual norm
+    (the first of equal ones), so it is never worse than s_0.  Returns
+    dict(u, history = ||r_n|| / ||Pi Y^T P d0|| before each correction and
+    after the last, best = the index of u in that history)."""
     lmax = sht.lmax
     st = setup(sht.grid, ncov, obs, d)
     tau, K = st["tau"], st["K"]
@@ -347,15 +350,18 @@ def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
         return float(np.sqrt(sum(alm_dot(r[f], r[f], lmax) for f in range(3))) / ny)
 
     s = messenger_run(sht, st["d0"], K, st["b"], tau, cl, lambda0, nsteps, iters)[0]
-    hist = []
+    hist, iterates = [], []
     for _ in range(ncorr):
         r = wf_residual(sht, s, st, cl)
         hist.append(rel_norm(r))
+        iterates.append(s)
         g = w * sht.synthesis(r)
         delta = messenger_run(sht, np.zeros_like(g), K, Tp * g, tau, cl, lambda0, nsteps, iters)[0]
         s = s + delta
     hist.append(rel_norm(wf_residual(sht, s, st, cl)))
-    return dict(u=s, history=hist)
+    iterates.append(s)
+    best = int(np.argmin(hist))
+    return dict(u=iterates[best], history=hist, best=best)
 
 
 # ----------------------------------------------------------------------------

@@ -399,7 +399,9 @@ void fixed_loop(dm_plan* p, int nrhs, double* alm, int64_t from, int64_t end, hi
 // from t = 0 with b = T_p g = -tau Y r~ (r~ = -r), so that every correction
 // applies one linear operator, and its fixed point solves the Wiener filter
 // equation exactly.  Records ||r|| / ||Pi Y^T P d0|| before each correction
-// and after the last in p->refine_hist.
+// and after the last in p->refine_hist, and returns per RHS the iterate of
+// smallest residual norm (the first of equal ones): the corrections
+// converge only where W~ is close enough to the inverse.
 void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, hipStream_t s) {
     const int64_t na2 = (int64_t)nrhs * 3 * p->nalm * 2;
     const int64_t nmap = (int64_t)nrhs * 3 * p->npix;
@@ -430,8 +432,22 @@ void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, hipStream_t s) 
             p->refine_hist[(size_t)k * nrhs + r] = ynorm[r] > 0.0 ? std::sqrt(q0) / ynorm[r] : 0.0;
         }
     };
+    // the best iterate so far per RHS (smallest residual norm), returned at the end
+    std::vector<double> best_r(nrhs);
+    const size_t slice = (size_t)3 * p->nalm * 2;
+    auto keep_best = [&](int k) {
+        for (int r = 0; r < nrhs; ++r) {
+            const double h = p->refine_hist[(size_t)k * nrhs + r];
+            if (k > 0 && !(h < best_r[r])) continue;
+            best_r[r] = h;
+            HIPCHK(hipMemcpyAsync(p->d_alm_best + slice * r, alm + slice * r, slice * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+    };
+    residual(0);
+    keep_best(0);
     for (int n = 0; n < p->refine; ++n) {
-        residual(n);
+        // d_alm_r holds r~ of the current iterate
         {
             PrecisionScope fp64(p, DM_FP64);
             alm2map_dev(p, nrhs, p->d_alm_r, p->d_ux, s);
@@ -450,11 +466,11 @@ void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, hipStream_t s) 
             throw;
         }
         std::swap(p->d_b, p->d_b2);
-        // the iterate before the last correction, for the final Cauchy ratio
-        if (n == p->refine - 1) HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
         HIPCHK(launch_axpby(alm, p->d_alm_corr, 1.0, 1.0, na2, s));
+        residual(n + 1);
+        keep_best(n + 1);
     }
-    residual(p->refine);
+    HIPCHK(hipMemcpyAsync(alm, p->d_alm_best, alm_bytes, hipMemcpyDeviceToDevice, s));
 }
 
 void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, hipStream_t s, dm_stats* stats,
@@ -632,7 +648,8 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         map2alm_dev(p, nrhs, p->d_b, p->d_alm_y, false, s);
         const int nb = alm_norm_blocks(p);
         double* parts = chi + (int64_t)nrhs * p->nrings;
-        HIPCHK(launch_alm_norms(p, nrhs, alm, eps ? nullptr : p->d_alm_prev, p->d_alm_r, p->d_alm_y, p->d_mats,
+        HIPCHK(launch_alm_norms(p, nrhs, alm, (eps || p->refine > 0) ? nullptr : p->d_alm_prev, p->d_alm_r, p->d_alm_y,
+                                p->d_mats,
                                 parts, s));
         std::vector<double> hchi((size_t)nrhs * p->nrings), hparts((size_t)nrhs * nb * kNormQ);
         HIPCHK(hipMemcpyAsync(hchi.data(), chi, hchi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -679,7 +696,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
     dfree(p->d_alm); dfree(p->d_alm_prev); dfree(p->d_alm_spin); dfree(p->d_d0); dfree(p->d_b); dfree(p->d_ux); dfree(p->d_alm_r);
     dfree(p->d_alm_y); dfree(p->d_filters); dfree(p->d_mats); dfree(p->d_red);
-    dfree(p->d_b2); dfree(p->d_alm_corr);
+    dfree(p->d_b2); dfree(p->d_alm_corr); dfree(p->d_alm_best);
     dfree(p->d_cpart); dfree(p->d_cout);
     if (p->h_cout) (void)hipHostFree(p->h_cout);
     if (p->h_pinned) (void)hipHostFree(p->h_pinned);
@@ -1314,6 +1331,7 @@ dm_status dm_set_refinement(dm_plan* p, int ncorrections) {
         if (ncorrections > 0 && !p->d_b2) {
             dalloc(p, p->d_b2, (size_t)p->max_rhs * 3 * p->npix);
             dalloc(p, p->d_alm_corr, (size_t)p->max_rhs * 3 * p->nalm * 2);
+            dalloc(p, p->d_alm_best, (size_t)p->max_rhs * 3 * p->nalm * 2);
         }
         p->refine = ncorrections;
     });

@@ -174,6 +174,7 @@ struct dm_plan {
     int refine = 0;
     double* d_b2 = nullptr;            // [B][3][npix]
     double* d_alm_corr = nullptr;      // [B][3][nalm] complex
+    double* d_alm_best = nullptr;      // [B][3][nalm] complex
     std::vector<double> refine_hist;
     int refine_nrhs = 0;
 

@@ -178,3 +178,27 @@ def test_refinement_off_and_refusals(dmwf, tmp_path):
     with pytest.raises(E) as e:
         plan.checkpoint_save(str(tmp_path / "r.ckpt"))
     assert e.value.status == dmwf.DM_ESTATE
+
+
+def test_stalling_corrections_return_the_best_iterate(dmwf):
+    """100:1 scan noise with holes on HEALPix at lmax = 2 Nside: the
+    corrections stall and then grow; each RHS returns the iterate of
+    smallest residual, as the oracle does."""
+    nside, lmax = 16, 32
+    p = inputs.make_problem(2, nside=nside, lmax=lmax, holes=20)
+    sht = SHT(healpix_grid(nside), lmax)
+    D = np.stack([sht.synthesis(inputs.signal_alm(2, lmax, k)) + inputs.noise_map(2, p["ncov"], p["obs"], k)
+                  for k in range(2)])
+    print("refinement past its best iterate", flush=True)
+    plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=2)
+    plan.set_spectra(p["cl"])
+    plan.set_noise(p["ncov"], p["obs"])
+    plan.set_schedule(1e3, 5, 10)
+    plan.set_refinement(8)
+    out = plan.wiener_filter(D)["alm"]
+    hist = plan.refinement_trace()
+    for k in range(2):
+        ref = dm.refine(sht, D[k], p["ncov"], p["obs"], p["cl"], 1e3, 5, 10, 8)
+        assert int(np.argmin(hist[:, k])) == ref["best"], (hist[:, k], ref["history"])
+        assert np.allclose(hist[:, k], ref["history"], rtol=1e-6, atol=0)
+        assert rel(out[k], ref["u"], lmax) < 1e-10, k
