@@ -688,7 +688,7 @@ void free_plan(dm_plan* p) {
         (void)hipEventDestroy(p->ev.stop[i]);
     }
     dfree(p->d_pair_x); dfree(p->d_pair_w); dfree(p->d_pair_one); dfree(p->d_pairs); dfree(p->d_fftlen);
-    dfree(p->d_plist_whole); dfree(p->d_plist_split);
+    dfree(p->d_plist_whole); dfree(p->d_plist_split); dfree(p->d_plist_small); dfree(p->d_plist_big);
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
     dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_coef_s); dfree(p->d_scale); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
@@ -851,6 +851,24 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
                 dalloc(p, p->d_plist_split, split.size());
                 if (!whole.empty()) upload(p, p->d_plist_whole, whole.data(), whole.size());
                 upload(p, p->d_plist_split, split.data(), split.size());
+                HIPCHK(hipStreamSynchronize(p->stream));
+            }
+            // size classes of the unsplit pairs (DMWF_RING_CLASSES=0 turns them off)
+            std::vector<int> small, big;
+            // (4096 + 512 + 8) x 16 B = 72 KB; DMWF_RING_SMALL_M lowers the
+            // bound, to exercise the two launches on small grids
+            const int kSmallM = std::max(4, std::min(4096, env_int("DMWF_RING_SMALL_M", 4096)));
+            for (int q : whole) (p->fft.M[pd[q].len_idx] <= kSmallM ? small : big).push_back(q);
+            if (env_int("DMWF_RING_CLASSES", 1) == 1 && !small.empty() && !big.empty()) {
+                p->ring_classes = 1;
+                p->n_small = (int)small.size();
+                p->n_big = (int)big.size();
+                for (int q : small) p->lds_small = std::max(p->lds_small, p->fft.M[pd[q].len_idx]);
+                for (int q : big) p->lds_big = std::max(p->lds_big, p->fft.M[pd[q].len_idx]);
+                dalloc(p, p->d_plist_small, small.size());
+                dalloc(p, p->d_plist_big, big.size());
+                upload(p, p->d_plist_small, small.data(), small.size());
+                upload(p, p->d_plist_big, big.data(), big.size());
                 HIPCHK(hipStreamSynchronize(p->stream));
             }
         }

@@ -120,6 +120,13 @@ struct dm_plan {
     int n_whole = 0, n_split = 0;
     int split_k = 2;                   // kappa values per lane of the split launch (2 or 4)
     int* d_plist_whole = nullptr;
+    // the unsplit pairs in two launches by transform size (ring_classes,
+    // used from 4 RHS per launch on): buffers up to 80 KB (two 512-thread
+    // workgroups per CU) and the rest (one 1024-thread workgroup per CU)
+    int ring_classes = 0;
+    int n_small = 0, n_big = 0, lds_small = 1, lds_big = 1;
+    int* d_plist_small = nullptr;
+    int* d_plist_big = nullptr;
     int* d_plist_split = nullptr;
     size_t fft_lds_bytes = 0;
 
