@@ -175,6 +175,7 @@ void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, dou
     const void* phase = phase_of(p, nrhs);
     const double* w = weighted ? p->d_pair_w : p->d_pair_one;
     int nslots = p->ana_chunks;
+    const bool partial32 = use_mfma(p, nrhs) && p->precision == DM_MIXED;
     {
         Timed t(p, KC_LEG_ANALYSIS, s);
         if (use_mfma(p, nrhs)) {
@@ -187,7 +188,8 @@ void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, dou
         t.done();
     }
     Timed t(p, KC_COMBINE, s);
-    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, filter, alm, spin, cpart, spin_scales(p, nrhs), s));
+    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, partial32, filter, alm, spin, cpart, spin_scales(p, nrhs),
+                          s));
     t.done();
 }
 

@@ -241,9 +241,11 @@ hipError_t launch_leg_synthesis(dm_plan* p, int nrhs, const double* spin_alm, do
 hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const double* pair_w,
                                double* partial, hipStream_t s);
 // scale (nullable): the batched kernels' recursion scales, applied to the
-// partial sums and to the spin-basis copy
-hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
-                          double* alm, double* spin, double* cpart, const double* scale, hipStream_t s);
+// partial sums and to the spin-basis copy; partial32: the slots hold FP32
+// (the mixed batched analysis), else FP64
+hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, bool partial32,
+                          const double* filter, double* alm, double* spin, double* cpart, const double* scale,
+                          hipStream_t s);
 int64_t cauchy_blocks(dm_plan* p);   // Cauchy partial sums per RHS written by the combine kernel
 hipError_t launch_cauchy_reduce(dm_plan* p, int nrhs, const double* cpart, double* out, hipStream_t s);
 hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, const double* scale,

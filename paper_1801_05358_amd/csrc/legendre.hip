@@ -571,8 +571,9 @@ __global__ __launch_bounds__(256) void cauchy_reduce_kernel(const double* __rest
 // kernels' recursion scales S (spin 0, spin 2); the partial sums are
 // multiplied by S, and so is the spin-basis copy (the batched synthesis
 // contracts the scaled functions with it).
+template <typename PV>
 __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, int nchunks, int nrhs,
-                                                      const double2* __restrict__ partial,
+                                                      const PV* __restrict__ partial,
                                                       const double* __restrict__ filt, double2* __restrict__ alm,
                                                       double2* __restrict__ spin, double* __restrict__ cpart,
                                                       const double* __restrict__ scale) {
@@ -587,9 +588,9 @@ __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, in
         for (int f = 0; f < 3; ++f) {
             double2 s = make_double2(0.0, 0.0);
             for (int c = 0; c < nchunks; ++c) {
-                const double2 v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
-                s.x += v.x;
-                s.y += v.y;
+                const PV v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
+                s.x += (double)v.x;
+                s.y += (double)v.y;
             }
             a[f] = s;
         }
@@ -702,12 +703,18 @@ void set_analysis_tiling(dm_plan* p, int R) {
     p->ana_chunks = p->ana_blocks * (kAnaThreads / 64);
 }
 
-hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, const double* filter,
-                          double* alm, double* spin, double* cpart, const double* scale, hipStream_t s) {
+hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, bool partial32,
+                          const double* filter, double* alm, double* spin, double* cpart, const double* scale,
+                          hipStream_t s) {
     dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
-    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
-                       reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
-                       reinterpret_cast<double2*>(spin), cpart, scale);
+    if (partial32)
+        hipLaunchKernelGGL(combine_kernel<float2>, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
+                           reinterpret_cast<const float2*>(partial), filter, reinterpret_cast<double2*>(alm),
+                           reinterpret_cast<double2*>(spin), cpart, scale);
+    else
+        hipLaunchKernelGGL(combine_kernel<double2>, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
+                           reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
+                           reinterpret_cast<double2*>(spin), cpart, scale);
     return hipGetLastError();
 }
 

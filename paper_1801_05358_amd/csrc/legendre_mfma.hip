@@ -506,10 +506,12 @@ __device__ __forceinline__ void rec_act(const BatchArgs& A, const double* __rest
     rec_activate(A, m, l, s);
 }
 
-template <typename T, int W>
+// PT: the partial-sum slots' type (FP32 on the mixed path, where the
+// products are FP32 already; the combine kernel sums the slots in FP64)
+template <typename T, int W, typename PT>
 __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typename Vec2<T>::t* __restrict__ phase,
                                                       const double* __restrict__ pair_w,
-                                                      double* __restrict__ partial) {
+                                                      PT* __restrict__ partial) {
     typedef typename Mfma<T>::v4 v4;
     constexpr int RL = ana_rl<T>();
     __shared__ T tile[W][ana_tile<T>()];
@@ -566,7 +568,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     if (m < 2) hi = max(hi, 2);
 
     const int nrhs = A.nrhs;
-    double* out = partial + ((int64_t)bp.x * nrhs * 3) * A.nalm * 2;
+    PT* out = partial + ((int64_t)bp.x * nrhs * 3) * A.nalm * 2;
     const int ncol = min(8, nrhs - rb);
     // degrees below the block's first active one: zero partial sums
     // (consecutive threads write consecutive (l, re/im))
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
         const int run = 2 * nl, total = run * 3 * ncol;
         for (int q = threadIdx.x; q < total; q += 64 * W) {
             const int fr = q / run, w = q - fr * run;           // fr = rhs * 3 + f within the tile
-            out[((int64_t)(rb * 3 + fr) * A.nalm + base + m) * 2 + w] = 0.0;
+            out[((int64_t)(rb * 3 + fr) * A.nalm + base + m) * 2 + w] = (PT)0;
         }
     }
     if (lo > lmax) return;
@@ -635,7 +637,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
             for (int w2 = 0; w2 < W; ++w2) sum += (double)red[qb][w2][ofs];
             const int l = l0 + r;
             if (l <= lmax && rb + rr < nrhs)
-                out[((int64_t)((rb + rr) * 3 + f) * A.nalm + base + l) * 2 + ri2] = sum;
+                out[((int64_t)((rb + rr) * 3 + f) * A.nalm + base + l) * 2 + ri2] = (PT)sum;
         }
     };
 
@@ -750,10 +752,10 @@ hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pa
     A.mchunk = p->ana_mchunk;
     dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
     if (p->precision == DM_MIXED)
-        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves>), grid, dim3(64 * kAnaWaves), 0, s, A,
-                           static_cast<const float2*>(phase), pair_w, partial);
+        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves, float>), grid, dim3(64 * kAnaWaves), 0, s, A,
+                           static_cast<const float2*>(phase), pair_w, reinterpret_cast<float*>(partial));
     else
-        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves / 2>), grid, dim3(32 * kAnaWaves), 0, s, A,
+        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves / 2, double>), grid, dim3(32 * kAnaWaves), 0, s, A,
                            static_cast<const double2*>(phase), pair_w, partial);
     return hipGetLastError();
 }
