@@ -1246,7 +1246,7 @@ dm_status dm_checkpoint_save(const dm_plan* cp, const char* path) {
         const std::string tmp = std::string(path) + ".tmp";
         std::FILE* f = std::fopen(tmp.c_str(), "wb");
         REQUIRE(f != nullptr, DM_EINVAL, "cannot open " + tmp + " for writing");
-        CkWriter w{f};
+        CkWriter w{f, CkSum{}};
         w.put(kCkMagic, sizeof kCkMagic);
         w.val<uint32_t>(kCkVersion);
         w.val<int32_t>(p->grid.kind);
@@ -1290,7 +1290,7 @@ dm_status dm_checkpoint_load(dm_plan* p, const char* path) {
         std::FILE* f = std::fopen(path, "rb");
         REQUIRE(f != nullptr, DM_EINVAL, std::string("cannot open ") + path);
         std::unique_ptr<std::FILE, int (*)(std::FILE*)> guard(f, &std::fclose);
-        CkReader r{f};
+        CkReader r{f, CkSum{}};
         char magic[8];
         r.get(magic, sizeof magic);
         REQUIRE(r.ok && std::memcmp(magic, kCkMagic, 8) == 0, DM_EINVAL, "not a checkpoint file");
