@@ -129,7 +129,8 @@ void* phase_of(dm_plan* p, int nrhs) { return phase32(p, nrhs) ? (void*)p->d_pha
 
 void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const double* b, hipStream_t s) {
     Timed t(p, KC_RING, s);
-    HIPCHK(launch_ring(p, mode, nrhs, in, out, p->d_K, b, phase_of(p, nrhs), phase32(p, nrhs), s));
+    const double* K = mode == RING_ANALYSIS6 ? p->d_tn6 : p->d_K;
+    HIPCHK(launch_ring(p, mode, nrhs, in, out, K, b, phase_of(p, nrhs), phase32(p, nrhs), s));
     t.done();
 }
 
@@ -137,13 +138,19 @@ void ring(dm_plan* p, int mode, int nrhs, const double* in, double* out, const d
 // messenger t = K u_x + b -> ring Fourier data of t; t_out (nullable)
 // receives t.  Diagonal noise runs it in one ring pass per field; 3x3 noise
 // couples the three fields of a pixel, which one ring pass holds one at a
-// time, so there it is synthesis, the 3x3 update and analysis in turn.
+// time, so there it is synthesis, then analysis with the 3x3 update applied
+// as each field is loaded (from the three fields of u_x), or (when t itself
+// is wanted, or with DMWF_FUSE6=0) the update as a pass of its own.
 void messenger_step(dm_plan* p, int nrhs, double* t_out, hipStream_t s) {
     if (p->ncov_layout != DM_NCOV_SYM6) {
         ring(p, RING_ITERATE, nrhs, nullptr, t_out, p->d_b, s);
         return;
     }
     ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+    if (!t_out && p->fuse6) {
+        ring(p, RING_ANALYSIS6, nrhs, p->d_ux, nullptr, p->d_b, s);
+        return;
+    }
     {
         Timed t(p, KC_PIXEL, s);
         HIPCHK(launch_update6(p, nrhs, p->d_ux, p->d_b, t_out, s));
@@ -814,6 +821,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         }
         HIPCHK(hipStreamCreate(&p->stream));
         p->graphs = env_int("DMWF_GRAPHS", 1) != 0;
+        p->fuse6 = env_int("DMWF_FUSE6", 1) != 0;
 
         // ring and pair tables
         std::vector<double> px(p->npairs), pw(p->npairs), one(p->npairs, 1.0);

@@ -124,6 +124,7 @@ struct dm_plan {
     // used from 4 RHS per launch on): buffers up to 80 KB (two 512-thread
     // workgroups per CU) and the rest (one 1024-thread workgroup per CU)
     int ring_classes = 0;
+    int fuse6 = 1;                     // 3x3 update inside the ring analysis pass
     int n_small = 0, n_big = 0, lds_small = 1, lds_big = 1;
     int* d_plist_small = nullptr;
     int* d_plist_big = nullptr;
@@ -262,10 +263,12 @@ hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pa
                        hipStream_t s);
 
 // ringfft.hip
-enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3 };
+enum RingMode { RING_ANALYSIS = 1, RING_SYNTH = 2, RING_ITERATE = 3, RING_ANALYSIS6 = 4 };
 // RING_ANALYSIS: map -> phase.  RING_SYNTH: phase -> map.
 // RING_ITERATE: phase -> (K x + b) -> phase.
 // RING_ITERATE with map_out != null also stores the updated messenger t.
+// RING_ANALYSIS6: u_x map -> (the 3x3 update t = u_x - T_p P_p u_x + b) ->
+// phase, with K the T_p P_p entries [6][npix] (II IQ IU QQ QU UU).
 // phase: FP32 ring data if phase32, else FP64
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out,
                        const double* K, const double* b, void* phase, bool phase32, hipStream_t s);

@@ -255,7 +255,31 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
     const int nt = blockDim.x, tid = threadIdx.x;
     const int mmax = A.mmax;
     const bool synth = (MODE == RING_SYNTH || MODE == RING_ITERATE);
-    const bool anal = (MODE == RING_ANALYSIS || MODE == RING_ITERATE);
+    const bool anal = (MODE == RING_ANALYSIS || MODE == RING_ITERATE || MODE == RING_ANALYSIS6);
+    // the analysis input of field f at pixel pix: the map, or (3x3 noise)
+    // the messenger t_f = u_x,f - (T_p P_p u_x)_f + b_f from the three fields
+    // of u_x, with the arithmetic of the separate 3x3 update pass
+    auto in_val = [&](int f, int64_t moff, int64_t pix) -> double {
+        if constexpr (MODE == RING_ANALYSIS6) {
+            const int64_t np = A.npix;
+            const int64_t base = moff - (int64_t)f * np + pix;
+            const double x0 = map_in[base], x1 = map_in[base + np], x2 = map_in[base + 2 * np];
+            double y, xf;
+            if (f == 0) {
+                y = Kp[pix] * x0 + Kp[np + pix] * x1 + Kp[2 * np + pix] * x2;
+                xf = x0;
+            } else if (f == 1) {
+                y = Kp[np + pix] * x0 + Kp[3 * np + pix] * x1 + Kp[4 * np + pix] * x2;
+                xf = x1;
+            } else {
+                y = Kp[2 * np + pix] * x0 + Kp[4 * np + pix] * x1 + Kp[5 * np + pix] * x2;
+                xf = x2;
+            }
+            return (xf - y) + bp[moff + pix];
+        } else {
+            return map_in[moff + pix];
+        }
+    };
     const CR* chirp = L.bluestein ? A.chirp + L.chirp_off : nullptr;
     const CR zero = mk<R>(0, 0);
     // split ring (n = 4 i): the buffer holds the length-n spectrum or ring in
@@ -346,16 +370,15 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
                     for (int jj = i4 + tid; jj < M; jj += nt) buf[pidx((int)brev(jj, logM), sh)] = zero;
                 __syncthreads();
             } else {
-                for (int q = tid; q < M; q += nt) {
-                    const int jp = (int)brev(q, logM);
+                for (int jp = tid; jp < M; jp += nt) {
                     CR a = zero;
                     if (jp < i4) {
                         const int j = 4 * jp + r;
-                        a.x = (R)map_in[moff + P_.off_n + j];
-                        a.y = P_.has_s ? (R)map_in[moff + P_.off_s + j] : R(0);
+                        a.x = (R)in_val(f, moff, P_.off_n + j);
+                        a.y = P_.has_s ? (R)in_val(f, moff, P_.off_s + j) : R(0);
                         a = cmul(a, chirp[jp]);
                     }
-                    buf[pidx(q, sh)] = a;
+                    buf[pidx((int)brev(jp, logM), sh)] = a;
                 }
                 __syncthreads();
             }
@@ -466,16 +489,17 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
             }
             __syncthreads();
         }
-        if (MODE == RING_ANALYSIS && !split) {
-            for (int q = tid; q < M; q += nt) {
-                const int j = (int)brev(q, logM);
+        if ((MODE == RING_ANALYSIS || MODE == RING_ANALYSIS6) && !split) {
+            // lanes take consecutive pixels j (coalesced reads); a_j goes to
+            // the bit-reversed slot
+            for (int j = tid; j < M; j += nt) {
                 CR a = zero;
                 if (j < n) {
-                    a.x = (R)map_in[moff + P_.off_n + j];
-                    a.y = P_.has_s ? (R)map_in[moff + P_.off_s + j] : R(0);
+                    a.x = (R)in_val(f, moff, P_.off_n + j);
+                    a.y = P_.has_s ? (R)in_val(f, moff, P_.off_s + j) : R(0);
                     if (L.bluestein) a = cmul(a, chirp[j]);
                 }
-                buf[pidx(q, sh)] = a;
+                buf[pidx((int)brev(j, logM), sh)] = a;
             }
             __syncthreads();
         }
@@ -577,6 +601,7 @@ void launch_ring_t(dm_plan* p, int mode, int nrhs, const double* map_in, double*
     switch (mode) {
         case RING_ANALYSIS: launch_both<RING_ANALYSIS, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
         case RING_SYNTH: launch_both<RING_SYNTH, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
+        case RING_ANALYSIS6: launch_both<RING_ANALYSIS6, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
         default: launch_both<RING_ITERATE, R, P>(p, Ar, map_in, map_out, K, b, ph, s); break;
     }
 }
@@ -592,6 +617,7 @@ hipError_t set_lds_modes(size_t bytes) {
     hipError_t e = set_lds_one<RING_ANALYSIS, SPLITK, R, P>(bytes);
     if (e == hipSuccess) e = set_lds_one<RING_SYNTH, SPLITK, R, P>(bytes);
     if (e == hipSuccess) e = set_lds_one<RING_ITERATE, SPLITK, R, P>(bytes);
+    if (e == hipSuccess) e = set_lds_one<RING_ANALYSIS6, SPLITK, R, P>(bytes);
     return e;
 }
 

@@ -189,3 +189,20 @@ def test_noise_argument_errors(dmwf):
     fresh = make_plan(dmwf, p, p["ncov6"])
     fresh.set_schedule(1e3, 2, 2)
     assert np.array_equal(u, fresh.wiener_filter(D[0])["alm"][0])
+
+
+@pytest.mark.parametrize("precision,nrhs", [("fp64", 1), ("fp64", 8), ("mixed", 2)])
+def test_fused_update_equals_separate_pass(dmwf, monkeypatch, precision, nrhs):
+    """The 3x3 update applied inside the ring analysis pass gives the solve
+    of the separate update pass (DMWF_FUSE6=0), to rounding."""
+    p, grid, sht, D = corr_cfg(1, nrhs=nrhs)
+    prec = dmwf.FP64 if precision == "fp64" else dmwf.MIXED
+    outs = []
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("DMWF_FUSE6", fuse)
+        plan = make_plan(dmwf, p, p["ncov6"], max_rhs=nrhs, precision=prec)
+        monkeypatch.delenv("DMWF_FUSE6")
+        plan.set_schedule(1e3, 4, 5)
+        outs.append(plan.wiener_filter(D)["alm"])
+    for k in range(nrhs):
+        assert rel_alm(outs[0][k], outs[1][k], p["lmax"]) < 1e-12, k
