@@ -1,0 +1,51 @@
+"""CPU checks of bench.py's host logic (no GPU): it refuses more than one
+GPU with a message, the committed traffic summaries still match the kernel
+sources they were measured on, and the kernel-time summary keeps each
+kernel's last dispatches (the run whose HIP-event times the bench
+reports), leaving out the autotuner's earlier candidate launches."""
+
+import csv
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+_spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+bench = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(bench)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_committed_traffic_matches_sources():
+    for kernel in ("legendre_analysis", "legendre_synthesis"):
+        rec = bench.read_traffic(kernel, "mixed", 8)
+        assert rec is not None and rec > 0, kernel
+
+
+def test_kernel_summary_keeps_the_last_dispatches(tmp_path):
+    stats = tmp_path / "stats.csv"
+    trace = tmp_path / "trace.csv"
+    with open(stats, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"])
+        w.writerow(["void bana_kernel<float, 8, float>(x)", 4, 0, 2500, 90.0, 1000, 4000])
+        w.writerow(["tiny_kernel", 1, 0, 10, 0.001, 10, 10])
+    with open(trace, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        # two candidate launches first (400 us), then two tuned ones (100 us, 300 us)
+        for did, dur in ((1, 400000), (2, 400000), (3, 100000), (4, 300000)):
+            w.writerow(["KERNEL_DISPATCH", did, "void bana_kernel<float, 8, float>(x)", 100, 100 + dur])
+    out = tmp_path / "summary.txt"
+    bench.kernel_summary(str(stats), str(trace), str(out), "cmd", "title", 2)
+    text = out.read_text()
+    assert "# command: cmd" in text and "tiny_kernel" not in text
+    last = [l for l in text.splitlines() if l.startswith("void bana_kernel") and l.split()[-2] == "2"]
+    assert last and float(last[0].split()[-1]) == 200.0
