@@ -141,7 +141,22 @@ int dm_device_count(void);
  * max_rhs right-hand sides per call, on HIP device `device`.  Builds ring
  * tables, recursion coefficients and the per-(m, ring) recursion seeds.
  * Returns DM_EDEVICE without a GPU, DM_EINVAL on bad sizes,
- * DM_EUNSUPPORTED for a ring length that this build's FFT cannot stage.  */
+ * DM_EUNSUPPORTED for a ring length that this build's FFT cannot stage.
+ *
+ * Environment variables read here, for tuning and testing; none changes a
+ * result beyond FP rounding except DMWF_RING_FP32:
+ *   DMWF_MFMA=0|1          batched matrix-core Legendre kernels off / on
+ *   DMWF_SYN_MCHUNK, DMWF_ANA_MCHUNK   their m-chunk per XCD (see dm_autotune)
+ *   DMWF_SYN_THREADS, DMWF_SYN_R, DMWF_ANA_R   single-RHS kernel tiling
+ *   DMWF_GRAPHS=0          fixed-schedule steps launched directly, not as graphs
+ *   DMWF_RING_THREADS=256|512|1024     whole-ring workgroup width
+ *   DMWF_RING_CLASSES=0    unsplit rings in one launch, not two by size
+ *   DMWF_RING_SMALL_M=n    size bound of the two launches (tests)
+ *   DMWF_FFT_MAX_ELEMS=n   largest unsplit transform buffer (tests: split rings)
+ *   DMWF_FUSE6=0           3x3 noise update as a pass of its own
+ *   DMWF_RING_FP32=1       FP32 ring transforms on DM_MIXED plans (lower
+ *                          accuracy: about 1.2e-5 at Nside 1024, past 1e-5)
+ *   DMWF_TUNE_CACHE=path   dm_autotune's cache file                       */
 dm_status dm_plan_create(dm_plan** plan, const dm_grid* grid, int lmax, int max_rhs,
                          dm_precision precision, int device);
 dm_status dm_plan_destroy(dm_plan* plan);
