@@ -182,14 +182,21 @@ def messenger_run(sht, t, K, b, tau, cl, lambda0, nsteps, iters_per_step):
     """Algorithm 1's loop under the fixed schedule from the messenger t,
     with the pixel update t = K u_x + b.  Returns (u, u_x = Y u, the
     per-iteration Cauchy ratios)."""
+    lams = schedule(lambda0, nsteps)
+    return messenger_run_counts(sht, t, K, b, tau, cl, lams, [iters_per_step] * len(lams))
+
+
+def messenger_run_counts(sht, t, K, b, tau, cl, lambdas, counts):
+    """The same loop with counts[k] iterations at cooling step k (lambda =
+    lambdas[k])."""
     lmax = sht.lmax
     u_prev = None
     cauchy = []
     u = ux = None
-    for lam in schedule(lambda0, nsteps):
+    for lam, count in zip(lambdas, counts):
         mu = (lam - 1.0) * tau
         F = messenger_filter(cl, mu, tau)
-        for _ in range(iters_per_step):
+        for _ in range(count):
             t_hat = sht.analysis(t)
             u = apply_blocks(F, t_hat, lmax)
             ux = sht.synthesis(u)
@@ -338,8 +345,32 @@ def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
     (the first of equal ones), so it is never worse than s_0.  Returns
     dict(u, history = ||r_n|| / ||Pi Y^T P d0|| before each correction and
     after the last, best = the index of u in that history)."""
-    lmax = sht.lmax
     st = setup(sht.grid, ncov, obs, d)
+    lams = schedule(lambda0, nsteps)
+    counts = [iters] * len(lams)
+    s0 = messenger_run_counts(sht, st["d0"], st["K"], st["b"], st["tau"], cl, lams, counts)[0]
+    return corrections(sht, st, cl, s0, lams, counts, ncorr)
+
+
+def refine_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters, ncorr):
+    """Appendix A's prescription under Algorithm 1's stopping rule: the first
+    solve runs with the Cauchy rule (solve_eps), the iterations it spent at
+    each cooling step are recorded, and every correction runs those counts
+    (so that W~ is one fixed operator).  Returns refine()'s dict plus
+    counts."""
+    r0 = solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters)
+    lams = r0["lambdas"]
+    counts = [r0["steps"].count(k) for k in range(len(lams))]
+    st = setup(sht.grid, ncov, obs, d)
+    out = corrections(sht, st, cl, r0["u"], lams, counts, ncorr)
+    out["counts"] = counts
+    return out
+
+
+def corrections(sht, st, cl, s, lambdas, counts, ncorr):
+    """The corrections of refine() from s_0 = s, W~ = the messenger run with
+    counts[k] iterations at lambdas[k]."""
+    lmax = sht.lmax
     tau, K = st["tau"], st["K"]
     w = pixel_weights(sht.grid)
     Tp = tau / w
@@ -349,14 +380,13 @@ def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
     def rel_norm(r):
         return float(np.sqrt(sum(alm_dot(r[f], r[f], lmax) for f in range(3))) / ny)
 
-    s = messenger_run(sht, st["d0"], K, st["b"], tau, cl, lambda0, nsteps, iters)[0]
     hist, iterates = [], []
     for _ in range(ncorr):
         r = wf_residual(sht, s, st, cl)
         hist.append(rel_norm(r))
         iterates.append(s)
         g = w * sht.synthesis(r)
-        delta = messenger_run(sht, np.zeros_like(g), K, Tp * g, tau, cl, lambda0, nsteps, iters)[0]
+        delta = messenger_run_counts(sht, np.zeros_like(g), K, Tp * g, tau, cl, lambdas, counts)[0]
         s = s + delta
     hist.append(rel_norm(wf_residual(sht, s, st, cl)))
     iterates.append(s)

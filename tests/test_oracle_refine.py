@@ -134,3 +134,19 @@ def test_divergent_corrections_return_the_best_iterate():
     y = dm.wf_residual(sht, np.zeros_like(r["u"]), st, p["cl"])
     got = norm(dm.wf_residual(sht, r["u"], st, p["cl"]), lmax) / norm(y, lmax)
     assert abs(got - min(h)) < 1e-12 * min(h)
+
+
+def test_eps_rule_refinement_reaches_dense_wiener_filter():
+    """Appendix A's own prescription: the first solve under the Cauchy rule
+    records its iterations per cooling step, and the corrections run those
+    counts; on the exact-quadrature grid they reach the dense Wiener filter."""
+    lmax = 6
+    sht, cl, ncov, obs, d = small_problem(gl_grid(lmax + 1, 2 * lmax + 1), lmax, seed=46)
+    wf = dense.wiener_filter(sht, d, ncov, obs, cl)
+    plain = dm.solve_eps(sht, d, ncov, obs, cl, 1e3, 0.5, 1e-2, 1e-3, 1.1, 2000)
+    r = dm.refine_eps(sht, d, ncov, obs, cl, 1e3, 0.5, 1e-2, 1e-3, 1.1, 2000, 4)
+    assert sum(r["counts"]) == plain["iterations"] and min(r["counts"]) >= 1
+    assert rel(plain["u"], wf, lmax) > 1e-5
+    assert rel(r["u"], wf, lmax) < 1e-10
+    h = r["history"]
+    assert all(h[k + 1] < 0.1 * h[k] for k in range(3)), h
