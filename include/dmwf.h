@@ -232,9 +232,12 @@ dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int 
  * (the first of equal ones): never worse than the plain solve.
  * ncorrections in [0, 1000], 0 = off (the default), else DM_EINVAL;
  * allocates a map and an alm buffer for max_rhs right-hand sides when
- * first enabled (DM_ENOMEM).  A refined solve needs the fixed schedule
- * without an iteration cap and no pending checkpoint (else
- * DM_EUNSUPPORTED from the solve), leaves nothing for
+ * first enabled (DM_ENOMEM).  In epsilon mode the first solve runs under
+ * the Cauchy rule and every correction runs the iterations it spent at
+ * each cooling step (Appendix A's prescription; dm_schedule_trace keeps the
+ * first solve's record).  A refined solve needs no iteration cap on the
+ * fixed schedule and no pending checkpoint (else DM_EUNSUPPORTED from the
+ * solve), leaves nothing for
  * dm_checkpoint_save, and reports in dm_stats the iterations of all runs
  * and `cauchy` = 0 (the residual history is the convergence record).      */
 dm_status dm_set_refinement(dm_plan* plan, int ncorrections);

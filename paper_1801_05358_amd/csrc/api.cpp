@@ -399,6 +399,32 @@ void fixed_loop(dm_plan* p, int nrhs, double* alm, int64_t from, int64_t end, hi
     }
 }
 
+// The messenger run with counts[k] iterations at cooling step k (the
+// iterations an epsilon-mode solve spent there), from the ring Fourier data
+// of the current messenger; it ends like fixed_loop.
+void counted_loop(dm_plan* p, int nrhs, double* alm, const std::vector<int>& counts, hipStream_t s,
+                  StepGraphs& graphs) {
+    const size_t per = (size_t)(p->lmax + 1) * 4;
+    const size_t alm_bytes = (size_t)nrhs * 3 * p->nalm * 2 * sizeof(double);
+    int64_t total = 0, done = 0;
+    for (int c : counts) total += c;
+    for (size_t k = 0; k < counts.size(); ++k) {
+        if (counts[k] <= 0) continue;
+        const double* F = p->d_filters + per * k;
+        const bool last_step = done + counts[k] == total;
+        const int run = last_step ? counts[k] - 1 : counts[k];
+        run_iterations(p, nrhs, F, alm, run, s, graphs);
+        done += run;
+        if (last_step) {
+            HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
+            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
+            leg_synthesis(p, nrhs, p->d_alm_spin, s);
+            ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
+            ++done;
+        }
+    }
+}
+
 // Appendix A's refinement (a modified Jacobi relaxation), on the sphere:
 // with W~ the fixed-schedule messenger run, p->refine corrections
 //   s <- s + W~(g),  g = W Y r,  r = Pi Y^T P (d0 - Y s) - S^+ s,
@@ -411,7 +437,7 @@ void fixed_loop(dm_plan* p, int nrhs, double* alm, int64_t from, int64_t end, hi
 // and after the last in p->refine_hist, and returns per RHS the iterate of
 // smallest residual norm (the first of equal ones): the corrections
 // converge only where W~ is close enough to the inverse.
-void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, hipStream_t s) {
+void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, const std::vector<int>* counts, hipStream_t s) {
     const int64_t na2 = (int64_t)nrhs * 3 * p->nalm * 2;
     const int64_t nmap = (int64_t)nrhs * 3 * p->npix;
     const size_t alm_bytes = (size_t)na2 * sizeof(double);
@@ -469,7 +495,10 @@ void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, hipStream_t s) 
             ring(p, RING_ANALYSIS, nrhs, p->d_ux, nullptr, nullptr, s);
             HIPCHK(hipMemsetAsync(p->d_alm_corr, 0, alm_bytes, s));
             StepGraphs graphs(s);
-            fixed_loop(p, nrhs, p->d_alm_corr, 0, full, s, graphs);
+            if (counts)
+                counted_loop(p, nrhs, p->d_alm_corr, *counts, s, graphs);
+            else
+                fixed_loop(p, nrhs, p->d_alm_corr, 0, full, s, graphs);
         } catch (...) {
             std::swap(p->d_b, p->d_b2);
             throw;
@@ -489,9 +518,8 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     check_rhs(p, nrhs);
     const auto t0 = std::chrono::steady_clock::now();
     if (p->refine > 0) {
-        REQUIRE(!eps_mode(p->sched), DM_EUNSUPPORTED,
-                "refinement needs the fixed schedule (every correction applies the same operator)");
-        REQUIRE(p->sched.max_iters <= 0, DM_EUNSUPPORTED, "refinement does not combine with an iteration cap");
+        REQUIRE(eps_mode(p->sched) || p->sched.max_iters <= 0, DM_EUNSUPPORTED,
+                "refinement does not combine with an iteration cap on the fixed schedule");
         REQUIRE(!p->resume.pending, DM_EUNSUPPORTED, "refinement does not resume from a checkpoint");
         // a refined solve leaves nothing to checkpoint
         p->state.valid = false;
@@ -556,7 +584,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         total = std::max(total, end);
         finished = total >= full;
         if (p->refine > 0) {
-            refine_dev(p, nrhs, alm, full, s);
+            refine_dev(p, nrhs, alm, full, nullptr, s);
             total *= 1 + p->refine;
         }
     } else {
@@ -620,6 +648,14 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 if (conv) break;
             }
         }
+        if (p->refine > 0) {
+            // Appendix A's prescription: every correction runs the
+            // iterations this solve spent at each cooling step
+            std::vector<int> counts(nsteps, 0);
+            for (int k : p->trace_step) ++counts[k];
+            refine_dev(p, nrhs, alm, 0, &counts, s);
+            total *= 1 + p->refine;
+        }
     }
     if (resumable) {
         // where this solve stopped, for dm_checkpoint_save
@@ -638,7 +674,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     // epilogue in FP64 (section a8): a mixed plan recomputes s_x = Y u with
     // the FP64 transforms before it is returned or enters the residual
     std::unique_ptr<PrecisionScope> fp64;
-    if ((p->precision == DM_MIXED || (p->refine > 0 && !eps)) && (map || stats)) {
+    if ((p->precision == DM_MIXED || p->refine > 0) && (map || stats)) {
         fp64.reset(new PrecisionScope(p, DM_FP64));
         alm2map_dev(p, nrhs, alm, p->d_ux, s);
     }
@@ -673,7 +709,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
             double c = 0;
             for (int j = 0; j < p->nrings; ++j) c += hchi[(size_t)r * p->nrings + j];
             stats[r].iterations = (int)total;
-            stats[r].cauchy = eps ? last_c[r] : (q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0);
+            stats[r].cauchy = p->refine > 0 ? 0.0 : eps ? last_c[r] : (q[1] > 0 ? std::sqrt(q[0] / q[1]) : 0.0);
             stats[r].residual = q[3] > 0 ? std::sqrt(q[2] / q[3]) : 0.0;
             stats[r].chi2 = c + q[4];
             stats[r].seconds = secs;

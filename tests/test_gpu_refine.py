@@ -7,8 +7,9 @@
   evaluated in FP64, also on DM_MIXED plans, whose plain solve stops at the
   FP32 level: mixed-precision defect correction.
 * Constrained realizations and correlated 3x3 noise with distinct masks go
-  through the same corrections; refinement off leaves solves bitwise
-  unchanged; unsupported combinations are refused.
+  through the same corrections; under the Cauchy rule the corrections run
+  the first solve's per-step counts, as the oracle's refine_eps(); refinement
+  off leaves solves bitwise unchanged; unsupported combinations are refused.
 """
 
 import numpy as np
@@ -164,10 +165,6 @@ def test_refinement_off_and_refusals(dmwf, tmp_path):
             plan.set_refinement(bad)
         assert e.value.status == dmwf.DM_EINVAL
     plan.set_refinement(2)
-    plan.set_schedule_eps(1e3, 0.5, 1e-2, 1e-3, 1.1, 200)
-    with pytest.raises(E) as e:
-        plan.wiener_filter(D[0])
-    assert e.value.status == dmwf.DM_EUNSUPPORTED
     plan.set_schedule(*SCHED, max_iters=5)
     with pytest.raises(E) as e:
         plan.wiener_filter(D[0])
@@ -202,3 +199,22 @@ def test_stalling_corrections_return_the_best_iterate(dmwf):
         assert int(np.argmin(hist[:, k])) == ref["best"], (hist[:, k], ref["history"])
         assert np.allclose(hist[:, k], ref["history"], rtol=1e-6, atol=0)
         assert rel(out[k], ref["u"], lmax) < 1e-10, k
+
+
+def test_eps_rule_refinement_matches_oracle(dmwf):
+    """Appendix A's prescription: epsilon-mode first solve, corrections with
+    its per-step iteration counts; the schedule trace stays the first
+    solve's."""
+    p, sht, D = cfg1(1)
+    print("refined solve under the Cauchy rule", flush=True)
+    args = (1e3, 0.5, 1e-2, 1e-3, 1.1, 2000)
+    plan = make_plan(dmwf, p, ncorr=2)
+    plan.set_schedule_eps(*args)
+    out = plan.wiener_filter(D[0], want_stats=True)
+    ref = dm.refine_eps(sht, D[0], p["ncov"], p["obs"], p["cl"], *args, 2)
+    plain = dm.solve_eps(sht, D[0], p["ncov"], p["obs"], p["cl"], *args)
+    trace, steps = plan.schedule_trace()
+    assert len(trace) == plain["iterations"] and np.array_equal(steps, plain["steps"])
+    assert out["stats"][0]["iterations"] == 3 * plain["iterations"]
+    assert rel(out["alm"][0], ref["u"], p["lmax"]) < 1e-10
+    assert np.allclose(plan.refinement_trace()[:, 0], ref["history"], rtol=1e-6, atol=0)
