@@ -140,6 +140,21 @@ def _f64(a, shape):
     return a.reshape(shape)
 
 
+def _dev(t, count, name):
+    """Pointer of a device tensor the library will read or write: float64,
+    on a GPU, contiguous, with exactly `count` elements (else ValueError, so
+    that no kernel sees a buffer of the wrong size)."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a GPU tensor")
+    if str(t.dtype) != "torch.float64":
+        raise ValueError(f"{name} must be float64, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != count:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {count}")
+    return _P(t.data_ptr())
+
+
 class Plan:
     """A solver plan: grid, band limit, batch capacity, precision, device."""
 
@@ -289,8 +304,9 @@ class Plan:
         nrhs = d.shape[0]
         stats = (DmStats * nrhs)() if want_stats else None
         sp = _P(stream.cuda_stream) if stream is not None else None
-        self._check(lib().dm_wiener_filter_device(self._h, nrhs, _P(d.data_ptr()), _P(alm.data_ptr()),
-                                                  _P(map.data_ptr()) if map is not None else None, sp, stats))
+        nm, na = nrhs * 3 * self.npix, nrhs * 3 * self.nalm * 2
+        self._check(lib().dm_wiener_filter_device(self._h, nrhs, _dev(d, nm, "d"), _dev(alm, na, "alm"),
+                                                  _dev(map, nm, "map") if map is not None else None, sp, stats))
         return [s.as_dict() for s in stats] if stats is not None else None
 
     def constrained_realizations(self, d, shat, dhat, want_f=False):
@@ -329,12 +345,18 @@ class Plan:
         return self._m2a(lib().dm_alm2map_adjoint, m)
 
     def alm2map_device(self, alm, map, stream=None):
+        """alm: torch float64 [nrhs, 3, 2 nalm] on the GPU; map: [nrhs, 3, npix]."""
+        nrhs = alm.shape[0]
         sp = _P(stream.cuda_stream) if stream is not None else None
-        self._check(lib().dm_alm2map_device(self._h, alm.shape[0], _P(alm.data_ptr()), _P(map.data_ptr()), sp))
+        self._check(lib().dm_alm2map_device(self._h, nrhs, _dev(alm, nrhs * 3 * self.nalm * 2, "alm"),
+                                            _dev(map, nrhs * 3 * self.npix, "map"), sp))
 
     def map2alm_device(self, map, alm, stream=None):
+        """map: torch float64 [nrhs, 3, npix] on the GPU; alm: [nrhs, 3, 2 nalm]."""
+        nrhs = map.shape[0]
         sp = _P(stream.cuda_stream) if stream is not None else None
-        self._check(lib().dm_map2alm_device(self._h, map.shape[0], _P(map.data_ptr()), _P(alm.data_ptr()), sp))
+        self._check(lib().dm_map2alm_device(self._h, nrhs, _dev(map, nrhs * 3 * self.npix, "map"),
+                                            _dev(alm, nrhs * 3 * self.nalm * 2, "alm"), sp))
 
     def iterate(self, d, t, lam, niter):
         d = np.asarray(d, dtype=np.float64)

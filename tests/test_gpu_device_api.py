@@ -1,0 +1,95 @@
+"""The device-pointer calls of the boundary (dm_wiener_filter_device,
+dm_alm2map_device, dm_map2alm_device) on caller-owned torch buffers: they
+give the host-pointer calls' results bit for bit, on a stream of the
+caller's and on the null stream; non-finite device data are refused with
+DM_EINVAL; the binding refuses tensors of the wrong type, size or layout
+before any kernel sees them."""
+
+import numpy as np
+import pytest
+
+from oracle.geometry import healpix_grid
+from oracle.sht import SHT
+from paper_1801_05358_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1801_05358_amd import dmwf
+    assert dmwf.device_count() > 0, "no GPU visible"
+    p = inputs.make_problem(1)
+    sht = SHT(healpix_grid(p["nside"]), p["lmax"])
+    D = np.stack([sht.synthesis(inputs.signal_alm(1, p["lmax"], k)) + inputs.noise_map(1, p["ncov"], p["obs"], k)
+                  for k in range(2)])
+    return torch, dmwf, p, D
+
+
+def make(dmwf, p, nrhs, prec):
+    plan = dmwf.Plan(lmax=p["lmax"], nside=p["nside"], max_rhs=nrhs, precision=prec)
+    plan.set_spectra(p["cl"])
+    plan.set_noise(p["ncov"], p["obs"])
+    plan.set_schedule(1e3, 3, 4)
+    return plan
+
+
+@pytest.mark.parametrize("precision,nrhs,own_stream", [("fp64", 1, True), ("mixed", 2, True), ("fp64", 1, False)])
+def test_device_solve_equals_host_solve(env, precision, nrhs, own_stream):
+    torch, dmwf, p, D = env
+    print(f"device solve {precision} nrhs={nrhs} own_stream={own_stream}", flush=True)
+    prec = dmwf.FP64 if precision == "fp64" else dmwf.MIXED
+    plan = make(dmwf, p, nrhs, prec)
+    host = plan.wiener_filter(D[:nrhs], want_map=True, want_stats=True)
+    dev = torch.device("cuda:0")
+    d_t = torch.from_numpy(np.ascontiguousarray(D[:nrhs])).to(dev)
+    a_t = torch.empty((nrhs, 3, plan.nalm * 2), dtype=torch.float64, device=dev)
+    m_t = torch.empty((nrhs, 3, plan.npix), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream() if own_stream else None
+    stats = plan.wiener_filter_device(d_t, a_t, m_t, stream=stream, want_stats=True)
+    torch.cuda.synchronize()
+    alm = a_t.cpu().numpy().view(np.complex128)
+    assert np.array_equal(alm, host["alm"])
+    assert np.array_equal(m_t.cpu().numpy(), host["map"])
+    for sd, sh in zip(stats, host["stats"]):
+        for k in ("iterations", "residual", "cauchy", "chi2"):
+            assert sd[k] == sh[k], k
+
+
+def test_device_transforms_equal_host_transforms(env):
+    torch, dmwf, p, D = env
+    plan = make(dmwf, p, 2, dmwf.FP64)
+    rng = np.random.default_rng(9)
+    a = plan.map2alm(D)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    m_t = torch.from_numpy(np.ascontiguousarray(D)).to(dev)
+    a_t = torch.empty((2, 3, plan.nalm * 2), dtype=torch.float64, device=dev)
+    plan.map2alm_device(m_t, a_t, stream=stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(a_t.cpu().numpy().view(np.complex128), a)
+    b = a * (1 + 0.1 * rng.standard_normal(a.shape))
+    b_t = torch.from_numpy(np.ascontiguousarray(b).view(np.float64)).to(dev)
+    o_t = torch.empty((2, 3, plan.npix), dtype=torch.float64, device=dev)
+    plan.alm2map_device(b_t, o_t, stream=stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(o_t.cpu().numpy(), plan.alm2map(b))
+
+
+def test_device_argument_errors(env):
+    torch, dmwf, p, D = env
+    plan = make(dmwf, p, 1, dmwf.FP64)
+    dev = torch.device("cuda:0")
+    a_t = torch.empty((1, 3, plan.nalm * 2), dtype=torch.float64, device=dev)
+    bad = torch.from_numpy(np.ascontiguousarray(D[:1])).to(dev)
+    bad[0, 1, 7] = float("nan")
+    with pytest.raises(dmwf.DmwfError) as e:
+        plan.wiener_filter_device(bad, a_t)
+    assert e.value.status == dmwf.DM_EINVAL
+    good = torch.from_numpy(np.ascontiguousarray(D[:1])).to(dev)
+    for wrong in (good.float(), good.cpu(), good[:, :, ::2], good[:, :2]):
+        with pytest.raises(ValueError):
+            plan.wiener_filter_device(wrong, a_t)
+    with pytest.raises(ValueError):
+        plan.wiener_filter_device(good, a_t[:, :, :-2])
