@@ -260,8 +260,8 @@ def main():
         kernel_summary(*args.kernel_summary, args.traffic_command, args.summary_title, args.summary_last)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); how the path would shard "
-              f"over several GPUs is described in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU "
+              f"path; batched right-hand sides would shard across GPUs without communication.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

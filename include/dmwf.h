@@ -58,7 +58,7 @@ typedef enum {
     DM_EDEVICE = -3,       /* no usable GPU, or a HIP runtime error     */
     DM_ENONFINITE = -4,    /* a non-finite value appeared in the iterate */
     DM_ESTATE = -5,        /* call out of order (e.g. no noise set yet)  */
-    DM_EUNSUPPORTED = -6   /* valid request that this build cannot run   */
+    DM_EUNSUPPORTED = -6   /* valid request that the library cannot run */
 } dm_status;
 
 typedef enum { DM_GRID_HEALPIX_RING = 0, DM_GRID_GAUSS_LEGENDRE = 1 } dm_grid_kind;
@@ -141,7 +141,7 @@ int dm_device_count(void);
  * max_rhs right-hand sides per call, on HIP device `device`.  Builds ring
  * tables, recursion coefficients and the per-(m, ring) recursion seeds.
  * Returns DM_EDEVICE without a GPU, DM_EINVAL on bad sizes,
- * DM_EUNSUPPORTED for a ring length that this build's FFT cannot stage.
+ * DM_EUNSUPPORTED for a ring length that the library's FFT cannot stage.
  *
  * Environment variables read here, for tuning and testing; none changes a
  * result beyond FP rounding except DMWF_RING_FP32:
