@@ -297,3 +297,35 @@ def test_full_size_sampled_transforms(nside, lmax, dmwf):
     for k, (l, mm) in enumerate(modes):
         got = alm[:, alm_index(l, mm, lmax)]
         assert np.abs(got - ref[:, k]).max() <= 1e-11 * scale, (l, mm, got, ref[:, k])
+
+
+def test_full_size_two_launch_ring_step(dmwf):
+    """Nside 1024, lmax 2048 with 4 RHS, where the unsplit rings run in two
+    launches by transform size: synthesis on sampled rings of the first and
+    the last RHS (rings of both size classes) and analysis on sampled (l, m),
+    each computed one by one by the oracle."""
+    nside, lmax, nrhs = 1024, 2048, 4
+    print("full-size two-launch ring step", flush=True)
+    rng = np.random.default_rng(77)
+    grid = healpix_grid(nside)
+    plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=nrhs)
+    sht = SHT(grid, lmax, cache_bytes=0)
+    a = np.stack([inputs.draw_signal(inputs.spectra(lmax), lmax, rng) for _ in range(nrhs)])
+    mp = plan.alm2map(a)
+    # polar rings with Bluestein buffers of 8192 (i > 512) and 4096 or less, the belt
+    rings = [3, 400, 511, 512, 700, 1023, 1024, 2047, 3000, 4000]
+    for k in (0, nrhs - 1):
+        for r, blk in zip(rings, sht.synthesis(a[k], rings=rings)):
+            o, n = grid["offset"][r], grid["nphi"][r]
+            err = np.abs(mp[k][:, o:o + n] - blk).max()
+            polar = r < nside or r >= 3 * nside
+            tol = (lmax ** 2 * 2.2e-16 * 4) if polar else 1e-11
+            assert err <= tol * np.abs(blk).max() + 1e-13, (k, r, err)
+    m = rng.standard_normal((nrhs, 3, grid["npix"]))
+    alm = plan.map2alm(m)
+    modes = [(0, 0), (3, 1), (lmax // 2, lmax // 2 - 1), (lmax, lmax), (lmax, 7), (1500, 900)]
+    ref = sht.adjoint_modes(m[nrhs - 1], modes) * pixel_weights(grid)[0]
+    scale = np.abs(ref).max()
+    for j, (l, mm) in enumerate(modes):
+        got = alm[nrhs - 1][:, alm_index(l, mm, lmax)]
+        assert np.abs(got - ref[:, j]).max() <= 1e-11 * scale, (l, mm)
