@@ -329,3 +329,38 @@ def test_full_size_two_launch_ring_step(dmwf):
     for j, (l, mm) in enumerate(modes):
         got = alm[nrhs - 1][:, alm_index(l, mm, lmax)]
         assert np.abs(got - ref[:, j]).max() <= 1e-11 * scale, (l, mm)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_batched_transforms(dmwf, precision):
+    """The headline launch configuration (Nside 1024, lmax 2048, 8 RHS) on
+    the batched matrix-core Legendre kernels: synthesis on sampled rings and
+    analysis on sampled (l, m) of the first and last RHS against the
+    oracle; FP64 to rounding, mixed within 1e-5 relative per field."""
+    nside, lmax, nrhs = 1024, 2048, 8
+    print(f"full-size batched transforms {precision}", flush=True)
+    rng = np.random.default_rng(88)
+    grid = healpix_grid(nside)
+    prec = dmwf.FP64 if precision == "fp64" else dmwf.MIXED
+    plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=nrhs, precision=prec)
+    sht = SHT(grid, lmax, cache_bytes=0)
+    a = np.stack([inputs.draw_signal(inputs.spectra(lmax), lmax, rng) for _ in range(nrhs)])
+    mp = plan.alm2map(a)
+    rings = [0, 300, 512, 1023, 2047, 3500, 4094]
+    for k in (0, nrhs - 1):
+        blocks = sht.synthesis(a[k], rings=rings)
+        got = np.concatenate([mp[k][:, grid["offset"][r]:grid["offset"][r] + grid["nphi"][r]] for r in rings], 1)
+        ref = np.concatenate(blocks, 1)
+        for f in range(3):
+            rel_err = np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])
+            assert rel_err < (1e-11 if precision == "fp64" else 1e-5), (k, f, rel_err)
+    del mp
+    m = rng.standard_normal((nrhs, 3, grid["npix"]))
+    alm = plan.map2alm(m)
+    modes = [(2, 0), (3, 1), (700, 699), (lmax, lmax), (lmax, 7), (1500, 900), (2000, 30)]
+    for k in (0, nrhs - 1):
+        ref = sht.adjoint_modes(m[k], modes) * pixel_weights(grid)[0]
+        got = np.stack([alm[k][:, alm_index(l, mm, lmax)] for l, mm in modes], 1)
+        for f in range(3):
+            rel_err = np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])
+            assert rel_err < (1e-11 if precision == "fp64" else 1e-5), (k, f, rel_err)
