@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 4
+#define DMWF_ABI_VERSION 5
 
 typedef enum {
     DM_OK = 0,
@@ -265,6 +265,16 @@ dm_status dm_wiener_filter(dm_plan* plan, int nrhs, const double* d, double* alm
  * a synchronisation at the end.                                          */
 dm_status dm_wiener_filter_device(dm_plan* plan, int nrhs, const void* d, void* alm, void* map,
                                   void* hip_stream, dm_stats* stats);
+
+/* Same with single-precision device I/O (float d [nrhs][3][npix], alm
+ * [nrhs][3][nalm][2], map nullable), for callers that keep FP32 maps, e.g.
+ * with a DM_MIXED plan: the inputs are widened to double on the device, the
+ * solve is the double-buffer one, and alm and map are rounded to float, so
+ * the results are those of dm_wiener_filter_device on the widened data,
+ * rounded.  Allocates device scratch for the double buffers (DM_ENOMEM);
+ * non-finite data are DM_EINVAL.                                          */
+dm_status dm_wiener_filter_device_f32(dm_plan* plan, int nrhs, const void* d, void* alm, void* map,
+                                      void* hip_stream, dm_stats* stats);
 
 /* Constrained realizations, eq 19: s_CR,k = W(d - d_hat_k) + s_hat_k for
  * k < nreal, run as one batch of nreal + 1 right-hand sides (the extra one

@@ -1463,6 +1463,39 @@ dm_status dm_wiener_filter_device(dm_plan* p, int nrhs, const void* d, void* alm
     });
 }
 
+dm_status dm_wiener_filter_device_f32(dm_plan* p, int nrhs, const void* d, void* alm, void* map, void* hip_stream,
+                                      dm_stats* stats) {
+    return guarded(p, [&] {
+        REQUIRE(d && alm, DM_EINVAL, "d and alm must not be null");
+        check_rhs(p, nrhs);
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        const int64_t nmap = (int64_t)nrhs * 3 * p->npix, nalm2 = (int64_t)nrhs * 3 * p->nalm * 2;
+        double *dd = nullptr, *da = nullptr, *dm = nullptr;
+        auto del = [](double* x) { if (x) (void)hipFree(x); };
+        HIPCHK(hipMalloc((void**)&dd, (size_t)nmap * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g1(dd, del);
+        HIPCHK(hipMalloc((void**)&da, (size_t)nalm2 * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g2(da, del);
+        if (map) HIPCHK(hipMalloc((void**)&dm, (size_t)nmap * sizeof(double)));
+        std::unique_ptr<double, decltype(del)> g3(dm, del);
+        sync_plan_stream_to(p, s);
+        HIPCHK(launch_widen(dd, static_cast<const float*>(d), nmap, s));
+        // the data must be finite (checked on the device)
+        int* d_cnt = reinterpret_cast<int*>(p->d_red);
+        HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(int), s));
+        HIPCHK(launch_count_nonfinite(dd, nmap, d_cnt, s));
+        int cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, d_cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        REQUIRE(cnt == 0, DM_EINVAL, "d must be finite");
+        solve_dev(p, nrhs, dd, da, dm, s, stats, true);
+        HIPCHK(launch_narrow(static_cast<float*>(alm), da, nalm2, s));
+        if (map) HIPCHK(launch_narrow(static_cast<float*>(map), dm, nmap, s));
+        // the scratch is freed when the guards go: wait for the narrowing
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
 dm_status dm_constrained_realizations(dm_plan* p, int nreal, const double* d, const double* shat_alm,
                                       const double* dhat, double* scr_alm, double* f_alm) {
     return guarded(p, [&] {

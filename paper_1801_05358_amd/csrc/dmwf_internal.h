@@ -300,6 +300,9 @@ int alm_norm_blocks(dm_plan* p);
 hipError_t launch_alm_norms(dm_plan* p, int nrhs, const double* u, const double* uprev, const double* r1,
                             const double* y1, const double* mats, double* parts, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* count, hipStream_t s);
+// y = (double) x, y = (float) x, elementwise
+hipError_t launch_widen(double* y, const float* x, int64_t n, hipStream_t s);
+hipError_t launch_narrow(float* y, const double* x, int64_t n, hipStream_t s);
 // y = a * x + c * y  (elementwise)
 hipError_t launch_axpby(double* y, const double* x, double a, double c, int64_t n, hipStream_t s);
 // refinement residual per (l, m): e <- Pi e + S^+ u in place; parts [blocks][2]

@@ -421,6 +421,12 @@ __global__ void scale_kernel(double* __restrict__ y, const double* __restrict__ 
         y[i] = a * x[i];
 }
 
+template <typename A, typename B>
+__global__ void convert_kernel(B* __restrict__ y, const A* __restrict__ x, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (B)x[i];
+}
+
 __global__ void count_nonfinite_kernel(const double* __restrict__ x, int64_t n, int* count) {
     int c = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -559,6 +565,18 @@ hipError_t launch_refine_residual(dm_plan* p, int nrhs, double* e, const double*
 hipError_t launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(kBlk), 0, s, y, x, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(double* y, const float* x, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_for(n)), dim3(kBlk), 0, s, y, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow(float* y, const double* x, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid_for(n)), dim3(kBlk), 0, s, y, x, n);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 # the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -86,6 +86,7 @@ def lib():
                                                 ctypes.POINTER(ctypes.c_int)]),
         "dm_wiener_filter": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, ctypes.POINTER(DmStats)]),
         "dm_wiener_filter_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
+        "dm_wiener_filter_device_f32": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
         "dm_constrained_realizations": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, _D, _D]),
         "dm_alm2map": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
         "dm_map2alm": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
@@ -117,7 +118,7 @@ def exported_symbols():
     return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
             "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_set_refinement",
             "dm_refinement_trace", "dm_wiener_filter",
-            "dm_wiener_filter_device",
+            "dm_wiener_filter_device", "dm_wiener_filter_device_f32",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
             "dm_map2alm_device", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
 
@@ -140,14 +141,14 @@ def _f64(a, shape):
     return a.reshape(shape)
 
 
-def _dev(t, count, name):
-    """Pointer of a device tensor the library will read or write: float64,
+def _dev(t, count, name, dtype="torch.float64"):
+    """Pointer of a device tensor the library will read or write: of dtype,
     on a GPU, contiguous, with exactly `count` elements (else ValueError, so
     that no kernel sees a buffer of the wrong size)."""
     if not getattr(t, "is_cuda", False):
         raise ValueError(f"{name} must be a GPU tensor")
-    if str(t.dtype) != "torch.float64":
-        raise ValueError(f"{name} must be float64, not {t.dtype}")
+    if str(t.dtype) != dtype:
+        raise ValueError(f"{name} must be {dtype[6:]}, not {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if t.numel() != count:
@@ -299,14 +300,19 @@ class Plan:
         return out
 
     def wiener_filter_device(self, d, alm, map=None, stream=None, want_stats=False):
-        """d: torch float64 [nrhs, 3, npix] on the GPU; alm: torch tensor of
-        nrhs*3*nalm complex doubles; map: optional torch [nrhs, 3, npix]."""
+        """d: torch [nrhs, 3, npix] on the GPU; alm: torch tensor of nrhs*3*nalm
+        complex values as (re, im) pairs; map: optional torch [nrhs, 3, npix].
+        All float64, or all float32 (dm_wiener_filter_device_f32)."""
         nrhs = d.shape[0]
         stats = (DmStats * nrhs)() if want_stats else None
         sp = _P(stream.cuda_stream) if stream is not None else None
         nm, na = nrhs * 3 * self.npix, nrhs * 3 * self.nalm * 2
-        self._check(lib().dm_wiener_filter_device(self._h, nrhs, _dev(d, nm, "d"), _dev(alm, na, "alm"),
-                                                  _dev(map, nm, "map") if map is not None else None, sp, stats))
+        dt = str(d.dtype)
+        if dt not in ("torch.float64", "torch.float32"):
+            raise ValueError(f"d must be float64 or float32, not {d.dtype}")
+        fn = lib().dm_wiener_filter_device if dt == "torch.float64" else lib().dm_wiener_filter_device_f32
+        self._check(fn(self._h, nrhs, _dev(d, nm, "d", dt), _dev(alm, na, "alm", dt),
+                       _dev(map, nm, "map", dt) if map is not None else None, sp, stats))
         return [s.as_dict() for s in stats] if stats is not None else None
 
     def constrained_realizations(self, d, shat, dhat, want_f=False):

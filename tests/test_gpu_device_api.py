@@ -93,3 +93,31 @@ def test_device_argument_errors(env):
             plan.wiener_filter_device(wrong, a_t)
     with pytest.raises(ValueError):
         plan.wiener_filter_device(good, a_t[:, :, :-2])
+
+
+@pytest.mark.parametrize("precision,nrhs", [("fp64", 1), ("mixed", 2)])
+def test_float32_device_io(env, precision, nrhs):
+    """dm_wiener_filter_device_f32: the double-buffer solve of the widened
+    data, rounded to float."""
+    torch, dmwf, p, D = env
+    print(f"float32 device I/O {precision}", flush=True)
+    prec = dmwf.FP64 if precision == "fp64" else dmwf.MIXED
+    plan = make(dmwf, p, nrhs, prec)
+    dev = torch.device("cuda:0")
+    d32 = torch.from_numpy(np.ascontiguousarray(D[:nrhs]).astype(np.float32)).to(dev)
+    a64 = torch.empty((nrhs, 3, plan.nalm * 2), dtype=torch.float64, device=dev)
+    m64 = torch.empty((nrhs, 3, plan.npix), dtype=torch.float64, device=dev)
+    plan.wiener_filter_device(d32.double(), a64, m64)
+    a32 = torch.empty((nrhs, 3, plan.nalm * 2), dtype=torch.float32, device=dev)
+    m32 = torch.empty((nrhs, 3, plan.npix), dtype=torch.float32, device=dev)
+    stream = torch.cuda.Stream()
+    plan.wiener_filter_device(d32, a32, m32, stream=stream)
+    torch.cuda.synchronize()
+    assert torch.equal(a32, a64.float()) and torch.equal(m32, m64.float())
+    bad = d32.clone()
+    bad[0, 2, 5] = float("inf")
+    with pytest.raises(dmwf.DmwfError) as e:
+        plan.wiener_filter_device(bad, a32)
+    assert e.value.status == dmwf.DM_EINVAL
+    with pytest.raises(ValueError):
+        plan.wiener_filter_device(d32, a64)
