@@ -309,8 +309,10 @@ void messenger_step(dm_plan* p, int nrhs, double* t_out, hipStream_t s);
 void run_iterations(dm_plan* p, int nrhs, const double* F, double* alm, int count, hipStream_t s, StepGraphs& g) {
     auto body = [&](hipStream_t st) {
         for (int i = 0; i < count; ++i) {
-            // t_hat = A t ; u = F t_hat   (eq 8) ; u_x = Y u ; t = K u_x + b ; next t_hat's ring data (eq 9)
-            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, st);
+            // t_hat = A t ; u = F t_hat   (eq 8) ; u_x = Y u ; t = K u_x + b ; next t_hat's ring data (eq 9).
+            // The next synthesis reads u through the spin-basis copy, so u
+            // itself is stored only by the run's last iteration
+            leg_analysis(p, nrhs, true, F, i == count - 1 ? alm : nullptr, p->d_alm_spin, st);
             leg_synthesis(p, nrhs, p->d_alm_spin, st);
             messenger_step(p, nrhs, nullptr, st);
         }

@@ -615,21 +615,25 @@ __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, in
             T = t2;
             E = e2;
         }
-        double2* o = alm + ((int64_t)rhs * 3) * nalm + idx;
-        if (cpart) {
-            const double w = m > 0 ? 2.0 : 1.0;
-            const double2 n3[3] = {T, E, B};
+        // alm may be null (a fixed-schedule iteration whose iterate only the
+        // next synthesis reads, through the spin-basis copy)
+        if (alm) {
+            double2* o = alm + ((int64_t)rhs * 3) * nalm + idx;
+            if (cpart) {
+                const double w = m > 0 ? 2.0 : 1.0;
+                const double2 n3[3] = {T, E, B};
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const double2 old = o[f * nalm];
-                const double dx = n3[f].x - old.x, dy = n3[f].y - old.y;
-                dd += w * (dx * dx + dy * dy);
-                nn += w * (n3[f].x * n3[f].x + n3[f].y * n3[f].y);
+                for (int f = 0; f < 3; ++f) {
+                    const double2 old = o[f * nalm];
+                    const double dx = n3[f].x - old.x, dy = n3[f].y - old.y;
+                    dd += w * (dx * dx + dy * dy);
+                    nn += w * (n3[f].x * n3[f].x + n3[f].y * n3[f].y);
+                }
             }
+            o[0] = T;
+            o[nalm] = E;
+            o[2 * nalm] = B;
         }
-        o[0] = T;
-        o[nalm] = E;
-        o[2 * nalm] = B;
         if (spin) {
             double2* q = spin + ((int64_t)rhs * 3) * nalm + idx;
             double2 p2, m2;
