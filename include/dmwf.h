@@ -32,8 +32,12 @@
  * Ownership The caller owns every buffer it passes.  Host-pointer calls copy
  *           inputs to the device and results back before returning.
  *           *_device calls borrow caller device buffers for the duration of
- *           the work they enqueue on the given HIP stream (NULL = the null
- *           stream) and return once it is enqueued.  The plan owns all other
+ *           the work they enqueue on the given HIP stream; NULL selects the
+ *           plan's own stream (a stream the plan creates, not the null
+ *           stream).  The single transforms (dm_alm2map_device,
+ *           dm_map2alm_device) return once their work is enqueued; the
+ *           Wiener filter calls return when it has finished (they read a
+ *           non-finite count back from the device).  The plan owns all other
  *           device memory.
  * Threads   A plan is not thread-safe: use it from one host thread at a time.
  * Errors    Every call returns dm_status (0 = DM_OK).  On error nothing is
@@ -49,7 +53,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 5
+#define DMWF_ABI_VERSION 6
 
 typedef enum {
     DM_OK = 0,
@@ -193,9 +197,11 @@ dm_status dm_set_noise(dm_plan* plan, const double* ncov, dm_ncov layout, const 
  * positive definite (its unobserved components enter through the
  * correlation matrix C); at least one observed component.  Entries of
  * pixels with nothing observed are ignored.  Another layout value is
- * DM_EUNSUPPORTED.  With DM_NCOV_SYM6 each iteration runs the pixel
- * update as its own pass over the maps (the three fields of a pixel are
- * coupled), so it costs a little more than diagonal noise.                */
+ * DM_EUNSUPPORTED.  With DM_NCOV_SYM6 the three fields of a pixel are
+ * coupled, so an iteration cannot keep one field's ring in fast memory from
+ * synthesis to analysis: it writes u_x = Y u and forms t from the three
+ * fields as the next ring analysis loads them, which costs a little more
+ * than diagonal noise (DMWF_FUSE6=0 runs the update as a pass of its own). */
 dm_status dm_set_noise_masks(dm_plan* plan, const double* ncov, dm_ncov layout, const uint8_t* obs_t,
                              const uint8_t* obs_p);
 
@@ -227,9 +233,10 @@ dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int 
  * Each correction costs one messenger run plus three FP64 transforms.  The
  * corrections converge only where W~ approximates the inverse well enough
  * (on Gauss-Legendre grids; on HEALPix with a moderate noise range and
- * mask); elsewhere they stall or grow, which dm_refinement_trace shows, so
- * each right-hand side returns the iterate of smallest residual norm seen
- * (the first of equal ones): never worse than the plain solve.
+ * mask); elsewhere they stall or grow, which dm_refinement_trace shows.
+ * A refined solve returns the last iterate, as Appendix A's relaxation
+ * does; dm_set_refinement_select can ask for the iterate of smallest
+ * residual norm instead.
  * ncorrections in [0, 1000], 0 = off (the default), else DM_EINVAL;
  * allocates a map and an alm buffer for max_rhs right-hand sides when
  * first enabled (DM_ENOMEM).  In epsilon mode the first solve runs under
@@ -241,6 +248,21 @@ dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int 
  * dm_checkpoint_save, and reports in dm_stats the iterations of all runs
  * and `cauchy` = 0 (the residual history is the convergence record).      */
 dm_status dm_set_refinement(dm_plan* plan, int ncorrections);
+
+/* Which iterate a refined solve returns: keep_best = 0 (the default) the
+ * last one, Appendix A's result; keep_best = 1, per right-hand side, the
+ * iterate of smallest ||r|| / ||Pi Y^T P d|| among the plain solve and the
+ * corrections (the first of equal ones), which is never worse than the
+ * plain solve where the corrections diverge.  Other values: DM_EINVAL.    */
+dm_status dm_set_refinement_select(dm_plan* plan, int keep_best);
+
+/* For the last refined solve, index[r] = the k of the iterate right-hand
+ * side r returned (k = 0 the plain solve, k = ncorrections the last
+ * correction; it indexes dm_refinement_trace's history).  Copies
+ * min(cap, n) entries to the caller's host array (NULL allowed) and sets
+ * *n to that solve's nrhs, 0 before any refined solve.  Errors: DM_EINVAL
+ * for a null plan or n.                                                   */
+dm_status dm_refinement_selected(const dm_plan* plan, int* index, int cap, int* n);
 
 /* Residual history of the last refined solve: history[k * nrhs + r] =
  * ||r_k|| / ||Pi Y^T P d|| for right-hand side r before correction k

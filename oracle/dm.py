@@ -326,7 +326,7 @@ def wf_residual(sht, s, st, cl):
     return apply_blocks(prior_range(cl), e, lmax) - apply_blocks(prior_pinv(cl), s, lmax)
 
 
-def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
+def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr, select="last"):
     """Appendix A's relaxation on the sphere: s_0 = W~ d (the fixed-schedule
     messenger run of solve()), then ncorr corrections
         s_{n+1} = s_n + W~(g_n),  g_n = W Y r_n,  r_n = wf_residual(s_n),
@@ -341,18 +341,20 @@ def refine(sht, d, ncov, obs, cl, lambda0, nsteps, iters, ncorr):
     flat-sky form (data minus W^+ s_n) needs a square, unitary basis change.
     The fixed point has r = 0 whenever Y^T W Y is invertible, whatever the
     grid and W~.  The corrections converge only where W~ is close enough to
-    the inverse; the result is the iterate with the smallest residual norm
-    (the first of equal ones), so it is never worse than s_0.  Returns
-    dict(u, history = ||r_n|| / ||Pi Y^T P d0|| before each correction and
-    after the last, best = the index of u in that history)."""
+    the inverse.  Appendix A's relaxation returns its last iterate
+    (select="last"); select="best" returns instead the iterate with the
+    smallest residual norm (the first of equal ones), never worse than s_0
+    where the corrections diverge.  Returns dict(u, history = ||r_n|| /
+    ||Pi Y^T P d0|| before each correction and after the last, best = the
+    index of the smallest entry of that history, chosen = the index of u)."""
     st = setup(sht.grid, ncov, obs, d)
     lams = schedule(lambda0, nsteps)
     counts = [iters] * len(lams)
     s0 = messenger_run_counts(sht, st["d0"], st["K"], st["b"], st["tau"], cl, lams, counts)[0]
-    return corrections(sht, st, cl, s0, lams, counts, ncorr)
+    return corrections(sht, st, cl, s0, lams, counts, ncorr, select)
 
 
-def refine_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters, ncorr):
+def refine_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters, ncorr, select="last"):
     """Appendix A's prescription under Algorithm 1's stopping rule: the first
     solve runs with the Cauchy rule (solve_eps), the iterations it spent at
     each cooling step are recorded, and every correction runs those counts
@@ -362,12 +364,12 @@ def refine_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, ma
     lams = r0["lambdas"]
     counts = [r0["steps"].count(k) for k in range(len(lams))]
     st = setup(sht.grid, ncov, obs, d)
-    out = corrections(sht, st, cl, r0["u"], lams, counts, ncorr)
+    out = corrections(sht, st, cl, r0["u"], lams, counts, ncorr, select)
     out["counts"] = counts
     return out
 
 
-def corrections(sht, st, cl, s, lambdas, counts, ncorr):
+def corrections(sht, st, cl, s, lambdas, counts, ncorr, select="last"):
     """The corrections of refine() from s_0 = s, W~ = the messenger run with
     counts[k] iterations at lambdas[k]."""
     lmax = sht.lmax
@@ -391,7 +393,10 @@ def corrections(sht, st, cl, s, lambdas, counts, ncorr):
     hist.append(rel_norm(wf_residual(sht, s, st, cl)))
     iterates.append(s)
     best = int(np.argmin(hist))
-    return dict(u=iterates[best], history=hist, best=best)
+    if select not in ("last", "best"):
+        raise ValueError(f"select must be 'last' or 'best', not {select!r}")
+    chosen = best if select == "best" else len(iterates) - 1
+    return dict(u=iterates[chosen], history=hist, best=best, chosen=chosen)
 
 
 # ----------------------------------------------------------------------------

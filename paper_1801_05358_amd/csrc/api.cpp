@@ -436,9 +436,11 @@ void counted_loop(dm_plan* p, int nrhs, double* alm, const std::vector<int>& cou
 // from t = 0 with b = T_p g = -tau Y r~ (r~ = -r), so that every correction
 // applies one linear operator, and its fixed point solves the Wiener filter
 // equation exactly.  Records ||r|| / ||Pi Y^T P d0|| before each correction
-// and after the last in p->refine_hist, and returns per RHS the iterate of
-// smallest residual norm (the first of equal ones): the corrections
-// converge only where W~ is close enough to the inverse.
+// and after the last in p->refine_hist.  Returns the last iterate, as
+// Appendix A's relaxation does, or with p->refine_best per RHS the iterate
+// of smallest residual norm (the first of equal ones): the corrections
+// converge only where W~ is close enough to the inverse.  p->refine_chosen
+// records which one each RHS returned.
 void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, const std::vector<int>* counts, hipStream_t s) {
     const int64_t na2 = (int64_t)nrhs * 3 * p->nalm * 2;
     const int64_t nmap = (int64_t)nrhs * 3 * p->npix;
@@ -469,14 +471,21 @@ void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, const std::vect
             p->refine_hist[(size_t)k * nrhs + r] = ynorm[r] > 0.0 ? std::sqrt(q0) / ynorm[r] : 0.0;
         }
     };
-    // the best iterate so far per RHS (smallest residual norm), returned at the end
+    // with refine_best: the best iterate so far per RHS (smallest residual
+    // norm), returned at the end
     std::vector<double> best_r(nrhs);
+    p->refine_chosen.assign(nrhs, 0);
     const size_t slice = (size_t)3 * p->nalm * 2;
     auto keep_best = [&](int k) {
         for (int r = 0; r < nrhs; ++r) {
             const double h = p->refine_hist[(size_t)k * nrhs + r];
+            if (!p->refine_best) {
+                p->refine_chosen[r] = k;
+                continue;
+            }
             if (k > 0 && !(h < best_r[r])) continue;
             best_r[r] = h;
+            p->refine_chosen[r] = k;
             HIPCHK(hipMemcpyAsync(p->d_alm_best + slice * r, alm + slice * r, slice * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
         }
@@ -510,7 +519,7 @@ void refine_dev(dm_plan* p, int nrhs, double* alm, int64_t full, const std::vect
         residual(n + 1);
         keep_best(n + 1);
     }
-    HIPCHK(hipMemcpyAsync(alm, p->d_alm_best, alm_bytes, hipMemcpyDeviceToDevice, s));
+    if (p->refine_best) HIPCHK(hipMemcpyAsync(alm, p->d_alm_best, alm_bytes, hipMemcpyDeviceToDevice, s));
 }
 
 void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, hipStream_t s, dm_stats* stats,
@@ -1401,6 +1410,22 @@ dm_status dm_set_refinement(dm_plan* p, int ncorrections) {
         }
         p->refine = ncorrections;
     });
+}
+
+dm_status dm_set_refinement_select(dm_plan* p, int keep_best) {
+    return guarded(p, [&] {
+        REQUIRE(keep_best == 0 || keep_best == 1, DM_EINVAL, "keep_best must be 0 or 1");
+        p->refine_best = keep_best;
+    });
+}
+
+dm_status dm_refinement_selected(const dm_plan* p, int* index, int cap, int* n) {
+    if (!p || !n) return DM_EINVAL;
+    const int cnt = (int)p->refine_chosen.size();
+    const int k = std::max(0, std::min(cap, cnt));
+    if (index) std::copy(p->refine_chosen.begin(), p->refine_chosen.begin() + k, index);
+    *n = cnt;
+    return DM_OK;
 }
 
 dm_status dm_refinement_trace(const dm_plan* p, double* history, int cap, int* n, int* nrhs) {

@@ -182,9 +182,11 @@ struct dm_plan {
     int refine = 0;
     double* d_b2 = nullptr;            // [B][3][npix]
     double* d_alm_corr = nullptr;      // [B][3][nalm] complex
-    double* d_alm_best = nullptr;      // [B][3][nalm] complex
+    double* d_alm_best = nullptr;      // [B][3][nalm] complex (refine_best only)
     std::vector<double> refine_hist;
     int refine_nrhs = 0;
+    int refine_best = 0;               // 0: the last iterate (Appendix A), 1: the one of smallest residual
+    std::vector<int> refine_chosen;    // [nrhs] index in refine_hist of the returned iterate
 
     // input fingerprints (checked when a solve resumes from a checkpoint)
     uint64_t hash_cl = 0, hash_noise = 0;

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 # the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -60,14 +60,40 @@ _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 
 
+def hip_runtimes():
+    """Distinct HIP runtime files (libamdhip64) mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln})
+    except OSError:
+        return []
+
+
 def lib():
-    """Load libdmwf.so (once).  Raises if it has not been built."""
+    """Load libdmwf.so (once).  Raises if it has not been built.
+
+    PyTorch ships its own HIP runtime (torch/lib/libamdhip64.so, soname
+    libamdhip64.so.7).  Loaded after the library, torch would bring a second
+    runtime into the process, and the device calls would hand torch's
+    streams and allocations to the other one.  So torch, when it is
+    installed, is imported first: the library's libamdhip64.so.7 then
+    resolves to the runtime already loaded.  The load is refused if two
+    runtimes are mapped all the same (e.g. the library was loaded through
+    another path before torch)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1801_05358_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads torch's HIP runtime before the library's)
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
+    rts = hip_runtimes()
+    if len(rts) > 1:
+        raise RuntimeError("two HIP runtimes are mapped into this process (" + ", ".join(rts) +
+                           "): import torch before anything loads libdmwf.so")
     sig = {
         "dm_abi_version": (ctypes.c_int, []),
         "dm_device_count": (ctypes.c_int, []),
@@ -84,6 +110,9 @@ def lib():
         "dm_set_refinement": (ctypes.c_int, [_P, ctypes.c_int]),
         "dm_refinement_trace": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int)]),
+        "dm_set_refinement_select": (ctypes.c_int, [_P, ctypes.c_int]),
+        "dm_refinement_selected": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_int)]),
         "dm_wiener_filter": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, _D, ctypes.POINTER(DmStats)]),
         "dm_wiener_filter_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
         "dm_wiener_filter_device_f32": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(DmStats)]),
@@ -117,7 +146,7 @@ def exported_symbols():
     """Names declared in include/dmwf.h that the binding expects."""
     return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
             "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_set_refinement",
-            "dm_refinement_trace", "dm_wiener_filter",
+            "dm_refinement_trace", "dm_set_refinement_select", "dm_refinement_selected", "dm_wiener_filter",
             "dm_wiener_filter_device", "dm_wiener_filter_device_f32",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
             "dm_map2alm_device", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
@@ -260,6 +289,21 @@ class Plan:
     def set_refinement(self, ncorrections):
         """Appendix A's corrections after every later solve (0 = off)."""
         self._check(lib().dm_set_refinement(self._h, int(ncorrections)))
+
+    def set_refinement_select(self, keep_best):
+        """Return the last iterate (False, Appendix A) or the iterate of
+        smallest residual (True) from a refined solve."""
+        self._check(lib().dm_set_refinement_select(self._h, 1 if keep_best else 0))
+
+    def refinement_selected(self):
+        """Per RHS of the last refined solve, the index (into
+        refinement_trace()'s rows) of the iterate it returned."""
+        n = ctypes.c_int(0)
+        self._check(lib().dm_refinement_selected(self._h, None, 0, ctypes.byref(n)))
+        idx = np.zeros(n.value, dtype=np.int32)
+        self._check(lib().dm_refinement_selected(self._h, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                                 n.value, ctypes.byref(n)))
+        return idx
 
     def refinement_trace(self):
         """Relative residual norms of the last refined solve, [ncorr + 1, nrhs]

@@ -5,7 +5,8 @@ oracle's results.  Calls only oracle/ and the seeded input generators.
 Stored: the spectra, the noise variances, the mask and the data (inputs),
 then the oracle's analysis A d, its plain solve (Algorithm 1 under the
 fixed cooling, 3 steps x 4 iterations from lambda 1e3) and the solve with
-two corrections of Appendix A's relaxation.  Usage:
+two corrections of Appendix A's relaxation (its last iterate, and the
+iterate of smallest residual).  Usage:
     python tests/golden/make_golden.py
 """
 
@@ -40,6 +41,7 @@ def results(p, sht, d):
         "analysis": sht.analysis(d),
         "u_plain": dm.solve(sht, d, p["ncov"], p["obs"], p["cl"], *SCHED)["u"],
         "u_refined": dm.refine(sht, d, p["ncov"], p["obs"], p["cl"], *SCHED, NCORR)["u"],
+        "u_refined_best": dm.refine(sht, d, p["ncov"], p["obs"], p["cl"], *SCHED, NCORR, select="best")["u"],
     }
 
 
@@ -51,7 +53,8 @@ def write():
         "# Written by tests/golden/make_golden.py (oracle/ and the seeded inputs only).",
         f"# schedule: lambda0 {SCHED[0]:g}, {SCHED[1]} cooling steps x {SCHED[2]} iterations (Algorithm 1,",
         "# fixed cooling); refined: the same plus "
-        f"{NCORR} corrections of Appendix A's relaxation.",
+        f"{NCORR} corrections of Appendix A's relaxation, returning the last iterate",
+        "# (u_refined) or the iterate of smallest Wiener filter residual (u_refined_best).",
         "# alm: fields T, E, B; m-major triangular, index m (2 lmax + 1 - m) / 2 + l; 're im' per value.",
         "# Sections: name, shape, then one value (or one 're im' pair) per line.",
     ]

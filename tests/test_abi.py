@@ -5,6 +5,8 @@ plan when no GPU is present (no compute call is made here)."""
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import pytest
 
@@ -23,7 +25,8 @@ def declared_functions():
 def lib():
     if not os.path.exists(LIB):
         pytest.fail("libdmwf.so is not built: run `python -m paper_1801_05358_amd.build`")
-    return ctypes.CDLL(LIB)
+    from paper_1801_05358_amd import dmwf
+    return dmwf.lib()
 
 
 def test_header_declares_the_boundary():
@@ -46,7 +49,7 @@ def test_binding_covers_header():
 
 def test_abi_version(lib):
     lib.dm_abi_version.restype = ctypes.c_int
-    assert lib.dm_abi_version() == 5
+    assert lib.dm_abi_version() == 6
     from paper_1801_05358_amd import dmwf
     header = open(HEADER).read()
     assert f"#define DMWF_ABI_VERSION {dmwf.ABI_VERSION}\n" in header
@@ -78,3 +81,44 @@ def test_product_path_has_no_cpu_fallback():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+_RUNTIMES = """
+import sys
+sys.path.insert(0, {root!r})
+from paper_1801_05358_amd import dmwf
+dmwf.lib()
+import torch
+print(len(dmwf.hip_runtimes()), dmwf.hip_runtimes())
+"""
+
+
+def test_one_hip_runtime_when_the_binding_loads_first():
+    """Loading the binding before torch must leave one HIP runtime mapped:
+    torch's own copy, which the library's libamdhip64.so.7 resolves to."""
+    r = subprocess.run([sys.executable, "-c", _RUNTIMES.format(root=ROOT)], capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stderr
+    n = int(r.stdout.split()[0])
+    assert n == 1, r.stdout
+
+
+_TWO = """
+import ctypes, sys
+sys.path.insert(0, {root!r})
+ctypes.CDLL({lib!r})          # the library's own runtime first, bypassing the binding
+from paper_1801_05358_amd import dmwf
+try:
+    dmwf.lib()
+except RuntimeError as e:
+    print("refused", e)
+else:
+    print("loaded", dmwf.hip_runtimes())
+"""
+
+
+def test_binding_refuses_two_hip_runtimes():
+    r = subprocess.run([sys.executable, "-c", _TWO.format(root=ROOT, lib=LIB)], capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("refused") and "two HIP runtimes" in r.stdout, r.stdout

@@ -35,6 +35,8 @@ def test_oracle_reproduces_stored_results():
         "analysis": sht.analysis(g["d"]),
         "u_plain": dm.solve(sht, g["d"], g["ncov"], obs, g["cl"], *golden.SCHED)["u"],
         "u_refined": dm.refine(sht, g["d"], g["ncov"], obs, g["cl"], *golden.SCHED, golden.NCORR)["u"],
+        "u_refined_best": dm.refine(sht, g["d"], g["ncov"], obs, g["cl"], *golden.SCHED, golden.NCORR,
+                                    select="best")["u"],
     }
     for k, v in got.items():
         assert np.abs(v - g[k]).max() <= 1e-12 * np.abs(g[k]).max(), k

@@ -1,7 +1,7 @@
 """The library on the stored tiny problem of tests/golden/dm_nside2_lmax4.txt
 (HEALPix Nside 2, lmax 4; the oracle's results written by
 tests/golden/make_golden.py): analysis to 1e-12, the plain and the refined
-solve to 1e-10 on the FP64 path, the plain solve within 1e-5 per field on
+solve (last and best iterate) to 1e-10 on the FP64 path, the plain solve within 1e-5 per field on
 the batched mixed path."""
 
 import importlib.util
@@ -53,6 +53,10 @@ def test_fp64_matches_stored_oracle_results(dmwf):
     u = plan.wiener_filter(g["d"])["alm"][0]
     for f in range(3):
         assert rel_field(u, g["u_refined"], f) < 1e-10, f
+    plan.set_refinement_select(True)
+    u = plan.wiener_filter(g["d"])["alm"][0]
+    for f in range(3):
+        assert rel_field(u, g["u_refined_best"], f) < 1e-10, f
 
 
 def test_mixed_matches_stored_oracle_results(dmwf):

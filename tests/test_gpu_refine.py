@@ -177,10 +177,12 @@ def test_refinement_off_and_refusals(dmwf, tmp_path):
     assert e.value.status == dmwf.DM_ESTATE
 
 
-def test_stalling_corrections_return_the_best_iterate(dmwf):
+def test_stalling_corrections_last_and_best_iterate(dmwf):
     """100:1 scan noise with holes on HEALPix at lmax = 2 Nside: the
-    corrections stall and then grow; each RHS returns the iterate of
-    smallest residual, as the oracle does."""
+    corrections stall and then grow.  By default each RHS returns the last
+    iterate (Appendix A); with the best-iterate selection the iterate of
+    smallest residual, as the oracle does in either case; the selected
+    indices are reported."""
     nside, lmax = 16, 32
     p = inputs.make_problem(2, nside=nside, lmax=lmax, holes=20)
     sht = SHT(healpix_grid(nside), lmax)
@@ -194,11 +196,19 @@ def test_stalling_corrections_return_the_best_iterate(dmwf):
     plan.set_refinement(8)
     out = plan.wiener_filter(D)["alm"]
     hist = plan.refinement_trace()
+    assert np.array_equal(plan.refinement_selected(), [8, 8])
+    plan.set_refinement_select(True)
+    best = plan.wiener_filter(D)["alm"]
+    assert np.array_equal(plan.refinement_trace(), hist)
+    chosen = plan.refinement_selected()
     for k in range(2):
         ref = dm.refine(sht, D[k], p["ncov"], p["obs"], p["cl"], 1e3, 5, 10, 8)
-        assert int(np.argmin(hist[:, k])) == ref["best"], (hist[:, k], ref["history"])
+        assert int(np.argmin(hist[:, k])) == ref["best"] == chosen[k], (hist[:, k], ref["history"], chosen)
         assert np.allclose(hist[:, k], ref["history"], rtol=1e-6, atol=0)
         assert rel(out[k], ref["u"], lmax) < 1e-10, k
+        ref_b = dm.refine(sht, D[k], p["ncov"], p["obs"], p["cl"], 1e3, 5, 10, 8, select="best")
+        assert rel(best[k], ref_b["u"], lmax) < 1e-10, k
+    assert dmwf.lib().dm_set_refinement_select(plan._h, 2) == dmwf.DM_EINVAL
 
 
 def test_eps_rule_refinement_matches_oracle(dmwf):

@@ -118,21 +118,28 @@ def test_correlated_noise_and_distinct_masks():
     assert all(h[k + 1] < 0.2 * h[k] for k in range(len(h) - 1)), h
 
 
-def test_divergent_corrections_return_the_best_iterate():
+def test_divergent_corrections_last_and_best_iterate():
     """With 100:1 scan noise and holes on HEALPix at lmax = 2 Nside the
     short messenger run is too rough an inverse and the corrections stall,
-    then grow; the result is the iterate of smallest residual, whose
-    residual is that minimum (recomputed here)."""
+    then grow.  Appendix A's relaxation returns the last iterate, whose
+    residual is the last entry of the history; select="best" returns the
+    iterate of smallest residual, whose residual is that minimum (both
+    recomputed here)."""
     nside, lmax = 16, 32
     p = inputs.make_problem(2, nside=nside, lmax=lmax, holes=20)
     sht = SHT(healpix_grid(nside), lmax)
     d = sht.synthesis(inputs.signal_alm(2, lmax, 0)) + inputs.noise_map(2, p["ncov"], p["obs"], 0)
-    r = dm.refine(sht, d, p["ncov"], p["obs"], p["cl"], 1e3, 5, 10, 8)
-    h = r["history"]
-    assert h[-1] > min(h) and 0 < r["best"] < len(h) - 1, h
     st = dm.setup(sht.grid, p["ncov"], p["obs"], d)
-    y = dm.wf_residual(sht, np.zeros_like(r["u"]), st, p["cl"])
-    got = norm(dm.wf_residual(sht, r["u"], st, p["cl"]), lmax) / norm(y, lmax)
+    y = dm.wf_residual(sht, np.zeros((3, (lmax + 1) * (lmax + 2) // 2), dtype=complex), st, p["cl"])
+    last = dm.refine(sht, d, p["ncov"], p["obs"], p["cl"], 1e3, 5, 10, 8)
+    h = last["history"]
+    assert h[-1] > min(h) and 0 < last["best"] < len(h) - 1, h
+    assert last["chosen"] == len(h) - 1
+    got = norm(dm.wf_residual(sht, last["u"], st, p["cl"]), lmax) / norm(y, lmax)
+    assert abs(got - h[-1]) < 1e-12 * h[-1]
+    best = dm.refine(sht, d, p["ncov"], p["obs"], p["cl"], 1e3, 5, 10, 8, select="best")
+    assert best["history"] == h and best["chosen"] == best["best"] == last["best"]
+    got = norm(dm.wf_residual(sht, best["u"], st, p["cl"]), lmax) / norm(y, lmax)
     assert abs(got - min(h)) < 1e-12 * min(h)
 
 
