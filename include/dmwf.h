@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 6
+#define DMWF_ABI_VERSION 7
 
 typedef enum {
     DM_OK = 0,
@@ -316,6 +316,24 @@ dm_status dm_alm2map_adjoint(dm_plan* plan, int nrhs, const double* map, double*
 /* Single transforms on device buffers (double), enqueued on hip_stream.   */
 dm_status dm_alm2map_device(dm_plan* plan, int nrhs, const void* alm, void* map, void* hip_stream);
 dm_status dm_map2alm_device(dm_plan* plan, int nrhs, const void* map, void* alm, void* hip_stream);
+
+/* dm_map2alm_device without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the ring Fourier data and the
+ * partial-sum slots of the analysis live in a fixed array of 32 MiB that
+ * the library's code object holds on every GPU it runs on (until the
+ * process ends), not in the plan's buffers.  Same arguments, layouts and
+ * results as dm_map2alm_device (the same kernels in the same order, so the
+ * same values to the last bit); map and alm are caller device buffers, work
+ * is enqueued on hip_stream (NULL = the plan's stream) and the call returns
+ * once it is enqueued.  The call does not wait for earlier work of the plan
+ * on other streams, and every call on one GPU shares its array, which keeps
+ * the last call's contents: calls that overlap on one GPU race.  A call
+ * whose work memory (ring data plus partial sums, for nrhs right-hand
+ * sides) exceeds 32 MiB is refused with DM_EINVAL and a message giving the
+ * size; DM_EDEVICE if the array's device address could not be obtained
+ * when the plan was created.  Per-kernel timing is off during the call.    */
+dm_status dm_map2alm_device_noalloc(dm_plan* plan, int nrhs, const void* map, void* alm, void* hip_stream);
 
 /* Run `niter` messenger iterations at a fixed lambda (mu = (lambda-1) tau)
  * from a given messenger map t_in [nrhs][3][npix] (no masking applied to

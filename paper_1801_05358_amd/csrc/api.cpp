@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,7 +19,42 @@
 
 using namespace dmwf;
 
+// Work memory of the allocation-free analysis (dm_map2alm_device_noalloc):
+// the ring Fourier data and the partial-sum slots of one call live in this
+// array, which the code object brings along, so that the call itself needs
+// no device allocation.  Every GPU the library runs on holds its own copy,
+// at its own address, until the process ends.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
 namespace {
+
+// Device addresses of `scratch`, one per device, looked up once with that
+// device current (the array's name is only a host-side stand-in).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Called at plan creation with `device` current.
+void scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+}
+
+void* scratch_of(int device, hipError_t* err) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
 
 thread_local std::string g_create_err;
 
@@ -826,6 +862,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
     p->precision = precision;
     try {
         HIPCHK(hipSetDevice(device));
+        scratch_setup(device);
         REQUIRE(precision == DM_FP64 || precision == DM_MIXED, DM_EINVAL, "unknown precision");
         REQUIRE(max_rhs >= 1 && max_rhs <= 4096, DM_EINVAL, "max_rhs must be in [1, 4096]");
         REQUIRE(lmax >= 2 && lmax <= 16384, DM_EINVAL, "lmax must be in [2, 16384]");
@@ -1614,6 +1651,53 @@ dm_status dm_map2alm_device(dm_plan* p, int nrhs, const void* map, void* alm, vo
             HIPCHK(hipStreamSynchronize(s));
             collect_events(p);
         }
+    });
+}
+
+dm_status dm_map2alm_device_noalloc(dm_plan* p, int nrhs, const void* map, void* alm, void* hip_stream) {
+    return guarded(p, [&] {
+        REQUIRE(alm && map, DM_EINVAL, "null argument");
+        check_rhs(p, nrhs);
+        hipError_t serr = hipSuccess;
+        char* base = static_cast<char*>(scratch_of(p->device, &serr));
+        REQUIRE(base != nullptr, DM_EDEVICE,
+                std::string("the device address of the scratch array is unknown: ") + hipGetErrorString(serr));
+        // the work memory map2alm_dev uses: ring Fourier data, then the
+        // analysis partial-sum slots, each as the plan's buffers would hold
+        // them for nrhs right-hand sides
+        const bool batched = use_mfma(p, nrhs);
+        const bool ring32 = phase32(p, nrhs);
+        const bool part32 = batched && p->precision == DM_MIXED;
+        const size_t phase_bytes = (size_t)nrhs * 3 * p->npairs * (p->mmax + 1) * 4 * (ring32 ? 4 : 8);
+        const size_t nslots = (size_t)(batched ? batched_analysis_slots(p) : p->ana_chunks);
+        const size_t part_bytes = nslots * nrhs * 3 * p->nalm * 2 * (part32 ? 4 : 8);
+        const size_t off = (phase_bytes + 255) / 256 * 256;
+        REQUIRE(off + part_bytes <= kScratchBytes, DM_EINVAL,
+                "this analysis needs " + std::to_string(off + part_bytes) + " bytes of work memory, more than the " +
+                    std::to_string(kScratchBytes) + " bytes of the allocation-free path: use dm_map2alm_device");
+        // the plan's work buffers stand aside for the call; per-kernel event
+        // timing (which creates events) is off during it
+        struct Swap {
+            dm_plan* p;
+            double* phase;
+            float* phase32;
+            double* partial;
+            bool profiling;
+            ~Swap() {
+                p->d_phase = phase;
+                p->d_phase32 = phase32;
+                p->d_partial = partial;
+                p->profiling = profiling;
+            }
+        } keep{p, p->d_phase, p->d_phase32, p->d_partial, p->profiling};
+        if (ring32)
+            p->d_phase32 = reinterpret_cast<float*>(base);
+        else
+            p->d_phase = reinterpret_cast<double*>(base);
+        p->d_partial = reinterpret_cast<double*>(base + off);
+        p->profiling = false;
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : p->stream;
+        map2alm_dev(p, nrhs, (const double*)map, (double*)alm, true, s);
     });
 }
 

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 # the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -122,6 +122,7 @@ def lib():
         "dm_alm2map_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
         "dm_alm2map_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
         "dm_map2alm_device": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+        "dm_map2alm_device_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
         "dm_set_noise_masks": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
                                               ctypes.POINTER(ctypes.c_uint8)]),
         "dm_autotune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
@@ -149,7 +150,7 @@ def exported_symbols():
             "dm_refinement_trace", "dm_set_refinement_select", "dm_refinement_selected", "dm_wiener_filter",
             "dm_wiener_filter_device", "dm_wiener_filter_device_f32",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
-            "dm_map2alm_device", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
+            "dm_map2alm_device", "dm_map2alm_device_noalloc", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
 
 
 def device_count():
@@ -407,6 +408,14 @@ class Plan:
         sp = _P(stream.cuda_stream) if stream is not None else None
         self._check(lib().dm_map2alm_device(self._h, nrhs, _dev(map, nrhs * 3 * self.npix, "map"),
                                             _dev(alm, nrhs * 3 * self.nalm * 2, "alm"), sp))
+
+    def map2alm_device_noalloc(self, map, alm, stream=None):
+        """map2alm_device with its work memory in the library's fixed
+        device array (no allocation; calls overlapping on one GPU race)."""
+        nrhs = map.shape[0]
+        sp = _P(stream.cuda_stream) if stream is not None else None
+        self._check(lib().dm_map2alm_device_noalloc(self._h, nrhs, _dev(map, nrhs * 3 * self.npix, "map"),
+                                                    _dev(alm, nrhs * 3 * self.nalm * 2, "alm"), sp))
 
     def iterate(self, d, t, lam, niter):
         d = np.asarray(d, dtype=np.float64)
