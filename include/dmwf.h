@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 7
+#define DMWF_ABI_VERSION 8
 
 typedef enum {
     DM_OK = 0,
@@ -215,6 +215,26 @@ dm_status dm_set_schedule(dm_plan* plan, const dm_schedule* schedule);
  * the iteration count; *n = 0 after a fixed-mode solve.  Errors: DM_EINVAL
  * for a null plan or n.                                                    */
 dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int cap, int* n);
+
+/* Diagnostics trace (Fig. 4's chi^2 and residual panels): with every > 0,
+ * every later Wiener filter solve evaluates, for the iterate u_i after
+ * iteration i (counted from the start of the schedule), the chi^2 of eq 3
+ * and the Appendix C residual, both as dm_stats defines them, whenever i is
+ * a multiple of `every` and after the solve's last iteration.  Each record
+ * costs one FP64 synthesis and one FP64 adjoint transform, and a traced
+ * solve launches its kernels directly (no graphs); the iterates themselves
+ * are unchanged.  Corrections of the refinement are not traced.  every = 0
+ * (the default) turns it off; every < 0 is DM_EINVAL.                      */
+dm_status dm_set_diagnostics(dm_plan* plan, int every);
+
+/* The trace of the last solve: iteration[k], and chi2[k * nrhs + r],
+ * residual[k * nrhs + r] for right-hand side r.  Copies min(cap, n)
+ * entries (times nrhs values) into the caller's host arrays (each may be
+ * NULL), sets *n to the entry count and *nrhs (nullable) to that solve's
+ * nrhs; both 0 when the last solve was not traced.  Errors: DM_EINVAL for a
+ * null plan or n.                                                         */
+dm_status dm_diagnostics_trace(const dm_plan* plan, int* iteration, double* chi2, double* residual, int cap, int* n,
+                               int* nrhs);
 
 /* Refinement by Appendix A's modified Jacobi relaxation: every later
  * Wiener filter solve (also inside dm_constrained_realizations) follows

@@ -169,13 +169,34 @@ def schedule(lambda0, nsteps):
 # ----------------------------------------------------------------------------
 # the iteration (Algorithm 1)
 # ----------------------------------------------------------------------------
-def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False):
+def diagnostics_recorder(sht, d, ncov, obs, cl, every):
+    """Per-iteration record of the diagnostics (Fig. 4): after iteration i
+    (counted from 1) whenever i is a multiple of ``every`` and after the
+    last one, the chi^2 of eq 3 and the Appendix C residual of the iterate
+    u_i.  Returns (record(u, i, last), the dict of lists it fills)."""
+    out = dict(iteration=[], chi2=[], residual=[])
+
+    def record(u, i, last):
+        if every <= 0 or not (i % every == 0 or last):
+            return
+        out["iteration"].append(i)
+        out["chi2"].append(chi2(sht, u, d, ncov, obs, cl))
+        out["residual"].append(residual(sht, u, d, ncov, obs, cl))
+    return record, out
+
+
+def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False, diagnostics_every=0):
     """Run the dual messenger loop.  Returns dict(u [3, nalm], ux = Y u
-    [3, npix], tau, cauchy (last), trace (list of per-iteration cauchy))."""
+    [3, npix], tau, cauchy (last), trace (list of per-iteration cauchy),
+    diagnostics (with diagnostics_every > 0: iteration, chi2, residual
+    lists, see diagnostics_recorder))."""
     st = setup(sht.grid, ncov, obs, d)
-    u, ux, cauchy = messenger_run(sht, st["d0"], st["K"], st["b"], st["tau"], cl, lambda0, nsteps, iters_per_step)
+    record, diag = diagnostics_recorder(sht, d, ncov, obs, cl, diagnostics_every)
+    lams = schedule(lambda0, nsteps)
+    u, ux, cauchy = messenger_run_counts(sht, st["d0"], st["K"], st["b"], st["tau"], cl, lams,
+                                         [iters_per_step] * len(lams), record=record)
     return dict(u=u, ux=ux, tau=st["tau"], cauchy=cauchy[-1] if cauchy else float("nan"),
-                trace=cauchy if trace else None, setup=st)
+                trace=cauchy if trace else None, setup=st, diagnostics=diag if diagnostics_every > 0 else None)
 
 
 def messenger_run(sht, t, K, b, tau, cl, lambda0, nsteps, iters_per_step):
@@ -186,19 +207,24 @@ def messenger_run(sht, t, K, b, tau, cl, lambda0, nsteps, iters_per_step):
     return messenger_run_counts(sht, t, K, b, tau, cl, lams, [iters_per_step] * len(lams))
 
 
-def messenger_run_counts(sht, t, K, b, tau, cl, lambdas, counts):
+def messenger_run_counts(sht, t, K, b, tau, cl, lambdas, counts, record=None):
     """The same loop with counts[k] iterations at cooling step k (lambda =
-    lambdas[k])."""
+    lambdas[k]); record (optional) is called as record(u_i, i, last) after
+    each iteration's harmonic update."""
     lmax = sht.lmax
     u_prev = None
     cauchy = []
     u = ux = None
+    total, i = sum(counts), 0
     for lam, count in zip(lambdas, counts):
         mu = (lam - 1.0) * tau
         F = messenger_filter(cl, mu, tau)
         for _ in range(count):
             t_hat = sht.analysis(t)
             u = apply_blocks(F, t_hat, lmax)
+            i += 1
+            if record is not None:
+                record(u, i, i == total)
             ux = sht.synthesis(u)
             t = pix_apply(K, ux) + b
             if u_prev is not None:
@@ -229,14 +255,15 @@ def eps_thresholds(nsteps, eps_start, eps_end, eta):
     return eps
 
 
-def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters):
+def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters, diagnostics_every=0):
     """Algorithm 1 with its stopping rule: at each cooling step repeat the
     iteration until ||u_i - u_{i-1}|| / ||u_i|| < eps_j (u_0 = 0, so every
     step runs at least one iteration), then cool; stop early once max_iters
     iterations have run in total.  Returns dict(u, ux, tau, iterations,
     trace = per-iteration Cauchy ratios, steps = cooling step of each
-    iteration)."""
+    iteration, diagnostics as in solve())."""
     lmax = sht.lmax
+    record, diag = diagnostics_recorder(sht, d, ncov, obs, cl, diagnostics_every)
     st = setup(sht.grid, ncov, obs, d)
     tau, K, b = st["tau"], st["K"], st["b"]
     t = st["d0"].copy()
@@ -256,11 +283,14 @@ def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max
             trace.append(c)
             steps.append(j)
             u_prev = u
+            last = (c < eps[j] and j == len(lams) - 1) or len(trace) >= max_iters
+            record(u, len(trace), last)
             if c < eps[j]:
                 break
         if len(trace) >= max_iters:
             break
-    return dict(u=u, ux=ux, tau=tau, iterations=len(trace), trace=trace, steps=steps, lambdas=lams, eps=eps)
+    return dict(u=u, ux=ux, tau=tau, iterations=len(trace), trace=trace, steps=steps, lambdas=lams, eps=eps,
+                diagnostics=diag if diagnostics_every > 0 else None)
 
 
 # ----------------------------------------------------------------------------

@@ -342,7 +342,63 @@ struct StepGraphs {
 
 void messenger_step(dm_plan* p, int nrhs, double* t_out, hipStream_t s);
 
+// Diagnostics of the iterate (Fig. 4), with the FP64 transforms in either
+// precision: chi^2 = (d0 - Y u)^T P (d0 - Y u) + u^T S^+ u (eq 3) and the
+// Appendix C residual ||S^+1/2 u + S^1/2 Y^T P (Y u - d0)|| / ||S^1/2 Y^T P d0||.
+// diag_prepare computes -Y^T P d0 into d_alm_y once per solve (only its norm
+// through S^1/2 enters); diag_record evaluates both for u = alm after
+// iteration `iter`.  Both run between an iteration's analysis and its
+// synthesis, where the map and ring buffers they use hold nothing live.
+void diag_prepare(dm_plan* p, int nrhs, hipStream_t s) {
+    PrecisionScope fp64(p, DM_FP64);
+    HIPCHK(hipMemsetAsync(p->d_ux, 0, (size_t)nrhs * 3 * p->npix * sizeof(double), s));
+    HIPCHK(launch_residual_maps(p, nrhs, p->d_ux, p->d_d0, nullptr, p->d_red + 64, s));
+    map2alm_dev(p, nrhs, p->d_ux, p->d_alm_y, false, s);
+}
+
+void diag_record(dm_plan* p, int nrhs, const double* alm, int64_t iter, hipStream_t s) {
+    PrecisionScope fp64(p, DM_FP64);
+    alm2map_dev(p, nrhs, alm, p->d_ux, s);
+    double* chi = p->d_red + 64;
+    HIPCHK(launch_residual_maps(p, nrhs, p->d_ux, p->d_d0, nullptr, chi, s));
+    map2alm_dev(p, nrhs, p->d_ux, p->d_alm_r, false, s);
+    const int nb = alm_norm_blocks(p);
+    double* parts = chi + (int64_t)nrhs * p->nrings;
+    HIPCHK(launch_alm_norms(p, nrhs, alm, nullptr, p->d_alm_r, p->d_alm_y, p->d_mats, parts, s));
+    std::vector<double> hchi((size_t)nrhs * p->nrings), hparts((size_t)nrhs * nb * kNormQ);
+    HIPCHK(hipMemcpyAsync(hchi.data(), chi, hchi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hparts.data(), parts, hparts.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p->diag_iter.push_back((int)iter);
+    for (int r = 0; r < nrhs; ++r) {
+        double q[kNormQ] = {0, 0, 0, 0, 0};
+        for (int b = 0; b < nb; ++b)
+            for (int k = 0; k < kNormQ; ++k) q[k] += hparts[((size_t)r * nb + b) * kNormQ + k];
+        double c = 0;
+        for (int j = 0; j < p->nrings; ++j) c += hchi[(size_t)r * p->nrings + j];
+        p->diag_chi2.push_back(c + q[4]);
+        p->diag_resid.push_back(q[3] > 0 ? std::sqrt(q[2] / q[3]) : 0.0);
+    }
+}
+
+// one more iteration of the solve has produced alm: record it if due
+void diag_after_analysis(dm_plan* p, int nrhs, const double* alm, bool last, hipStream_t s) {
+    if (!p->diag_active) return;
+    ++p->diag_count;
+    if (last || p->diag_count % p->diag_every == 0) diag_record(p, nrhs, alm, p->diag_count, s);
+}
+
 void run_iterations(dm_plan* p, int nrhs, const double* F, double* alm, int count, hipStream_t s, StepGraphs& g) {
+    if (p->diag_active) {
+        // traced: direct launches, the iterate stored after every analysis
+        for (int i = 0; i < count; ++i) {
+            leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
+            diag_after_analysis(p, nrhs, alm, false, s);
+            leg_synthesis(p, nrhs, p->d_alm_spin, s);
+            messenger_step(p, nrhs, nullptr, s);
+        }
+        return;
+    }
     auto body = [&](hipStream_t st) {
         for (int i = 0; i < count; ++i) {
             // t_hat = A t ; u = F t_hat   (eq 8) ; u_x = Y u ; t = K u_x + b ; next t_hat's ring data (eq 9).
@@ -431,6 +487,7 @@ void fixed_loop(dm_plan* p, int nrhs, double* alm, int64_t from, int64_t end, hi
         // ratio) and end with u_x = Y u
         HIPCHK(hipMemcpyAsync(p->d_alm_prev, alm, alm_bytes, hipMemcpyDeviceToDevice, s));
         leg_analysis(p, nrhs, true, F, alm, p->d_alm_spin, s);
+        diag_after_analysis(p, nrhs, alm, true, s);
         leg_synthesis(p, nrhs, p->d_alm_spin, s);
         ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
         ++it;
@@ -583,6 +640,18 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
 
     // setup: d0 = mask(d), b = T N^-1 d0
     HIPCHK(launch_data_setup(p, nrhs, d, p->d_d0, p->d_b, s));
+    // diagnostics trace of this solve's own iterations (a resumed solve
+    // counts on from its checkpoint)
+    p->diag_active = false;
+    p->diag_iter.clear();
+    p->diag_chi2.clear();
+    p->diag_resid.clear();
+    p->diag_nrhs = nrhs;
+    if (p->diag_every > 0) {
+        diag_prepare(p, nrhs, s);
+        p->diag_count = (resumable && p->resume.pending) ? p->resume.st.iterations : 0;
+        p->diag_active = true;
+    }
     const int nsteps = (int)lam.size();
     const bool eps = eps_mode(p->sched);
     const uint64_t hash_data = resumable ? device_hash(p, p->d_d0, (int64_t)nrhs * 3 * p->npix, 8, s) : 0;
@@ -628,6 +697,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         const int64_t end = p->sched.max_iters > 0 ? std::min<int64_t>(full, p->sched.max_iters) : full;
         if (rs) restart_from_u(total >= end);
         fixed_loop(p, nrhs, alm, total, end, s, graphs);
+        p->diag_active = false;
         total = std::max(total, end);
         finished = total >= full;
         if (p->refine > 0) {
@@ -671,7 +741,9 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 HIPCHK(hipMemcpyAsync(p->h_cout, p->d_cout, (size_t)nrhs * 2 * sizeof(double), hipMemcpyDeviceToHost,
                                       s));
                 HIPCHK(hipEventRecord(ev.e, s));
-                leg_synthesis(p, nrhs, p->d_alm_spin, s);
+                // traced: the diagnostics of this iterate go before its
+                // synthesis, once the ratio says whether it is the last
+                if (!p->diag_active) leg_synthesis(p, nrhs, p->d_alm_spin, s);
                 HIPCHK(hipEventSynchronize(ev.e));
                 double c = 0.0;
                 for (int r = 0; r < nrhs; ++r) {
@@ -686,6 +758,10 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 const bool conv = c < thr;
                 next_step = conv ? k + 1 : k;
                 finished = conv && k == nsteps - 1;
+                if (p->diag_active) {
+                    diag_after_analysis(p, nrhs, alm, finished || total >= sc.max_iters, s);
+                    leg_synthesis(p, nrhs, p->d_alm_spin, s);
+                }
                 if (finished || total >= sc.max_iters) {
                     ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);
                     done = true;
@@ -695,6 +771,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
                 if (conv) break;
             }
         }
+        p->diag_active = false;
         if (p->refine > 0) {
             // Appendix A's prescription: every correction runs the
             // iterations this solve spent at each cooling step
@@ -1472,6 +1549,27 @@ dm_status dm_refinement_trace(const dm_plan* p, double* history, int cap, int* n
     if (history) std::copy(p->refine_hist.begin(), p->refine_hist.begin() + k, history);
     *n = cnt;
     if (nrhs) *nrhs = cnt ? p->refine_nrhs : 0;
+    return DM_OK;
+}
+
+dm_status dm_set_diagnostics(dm_plan* p, int every) {
+    return guarded(p, [&] {
+        REQUIRE(every >= 0, DM_EINVAL, "every must be >= 0 (0: off)");
+        p->diag_every = every;
+    });
+}
+
+dm_status dm_diagnostics_trace(const dm_plan* p, int* iteration, double* chi2, double* residual, int cap, int* n,
+                               int* nrhs) {
+    if (!p || !n) return DM_EINVAL;
+    const int cnt = (int)p->diag_iter.size();
+    const int k = std::max(0, std::min(cap, cnt));
+    const size_t w = (size_t)std::max(p->diag_nrhs, 1);
+    if (iteration) std::copy(p->diag_iter.begin(), p->diag_iter.begin() + k, iteration);
+    if (chi2) std::copy(p->diag_chi2.begin(), p->diag_chi2.begin() + k * w, chi2);
+    if (residual) std::copy(p->diag_resid.begin(), p->diag_resid.begin() + k * w, residual);
+    *n = cnt;
+    if (nrhs) *nrhs = cnt ? p->diag_nrhs : 0;
     return DM_OK;
 }
 

@@ -188,6 +188,16 @@ struct dm_plan {
     int refine_best = 0;               // 0: the last iterate (Appendix A), 1: the one of smallest residual
     std::vector<int> refine_chosen;    // [nrhs] index in refine_hist of the returned iterate
 
+    // diagnostics trace (Fig. 4): chi^2 (eq 3) and the Appendix C residual
+    // of the iterate after every diag_every-th iteration and after the last;
+    // [entries][nrhs] per quantity, the iteration of each entry
+    int diag_every = 0;
+    bool diag_active = false;          // during a solve's own iterations (not refinement runs)
+    int64_t diag_count = 0;            // iterations of the current solve so far
+    int diag_nrhs = 0;
+    std::vector<int> diag_iter;
+    std::vector<double> diag_chi2, diag_resid;
+
     // input fingerprints (checked when a solve resumes from a checkpoint)
     uint64_t hash_cl = 0, hash_noise = 0;
     // where the last Wiener filter solve stopped: its iterate u in d_state_u,
@@ -287,7 +297,7 @@ hipError_t launch_noise_setup(dm_plan* p, const double* ncov, double tau, hipStr
 hipError_t launch_data_setup(dm_plan* p, int nrhs, const double* d, double* d0, double* b, hipStream_t s);
 // 3x3 noise, in place: ux <- ux - T P ux + b; t_out (nullable) gets a copy
 hipError_t launch_update6(dm_plan* p, int nrhs, double* ux, const double* b, double* t_out, hipStream_t s);
-// in place: ux <- N^-1 (ux - d0), b <- N^-1 d0;
+// in place: ux <- N^-1 (ux - d0), b <- N^-1 d0 (b nullable: not written);
 // chi_parts [nrhs][nrings] = sum (d0-ux)^T N^-1 (d0-ux)
 hipError_t launch_residual_maps(dm_plan* p, int nrhs, double* ux, const double* d0, double* b,
                                 double* chi_parts, hipStream_t s);

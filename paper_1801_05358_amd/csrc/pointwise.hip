@@ -255,7 +255,7 @@ __global__ void update6_kernel(int64_t npix, int nrhs, double* __restrict__ ux, 
     }
 }
 
-// grid (nrings, nrhs): ux <- P (ux - d0), b <- P d0,
+// grid (nrings, nrhs): ux <- P (ux - d0), b <- P d0 (b nullable),
 // chi_parts[rhs][ring] = sum (d0 - ux)^T P (d0 - ux)
 __global__ void resid6_kernel(int64_t npix, int nrings, const int64_t* __restrict__ roff,
                               const int* __restrict__ rn, const double* __restrict__ ninv6, double* __restrict__ ux,
@@ -278,15 +278,17 @@ __global__ void resid6_kernel(int64_t npix, int nrings, const int64_t* __restric
         ux[base] = y0;
         ux[base + npix] = y1;
         ux[base + 2 * npix] = y2;
-        b[base] = z0;
-        b[base + npix] = z1;
-        b[base + 2 * npix] = z2;
+        if (b) {
+            b[base] = z0;
+            b[base + npix] = z1;
+            b[base + 2 * npix] = z2;
+        }
     }
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) chi[(int64_t)rhs * nrings + r] = acc;
 }
 
-// grid (nrings, nrhs): ux <- N^-1 (ux - d0), b <- N^-1 d0,
+// grid (nrings, nrhs): ux <- N^-1 (ux - d0), b <- N^-1 d0 (b nullable),
 // chi_parts[rhs][ring] = sum (d0 - ux)^2 N^-1
 __global__ void resid_kernel(int64_t npix, int nrings, const int64_t* __restrict__ roff, const int* __restrict__ rn,
                              const double* __restrict__ ninv, double* __restrict__ ux,
@@ -304,7 +306,7 @@ __global__ void resid_kernel(int64_t npix, int nrings, const int64_t* __restrict
             const double res = ux[i] - d0[i];
             acc += res * res * ni;
             ux[i] = ni * res;
-            b[i] = ni * d0[i];
+            if (b) b[i] = ni * d0[i];
         }
     }
     acc = block_sum(acc, sh);

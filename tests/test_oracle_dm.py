@@ -264,3 +264,30 @@ def test_eps_mode_converges_to_exact_wiener_filter_on_gl():
         assert tr[st == j][-1] < r["eps"][j]
     firsts = [np.flatnonzero(st == j)[0] for j in range(1, len(r["lambdas"]))]
     assert all(tr[i] > tr[i - 1] for i in firsts)
+
+
+def test_diagnostics_record_the_iterates():
+    """The per-iteration record (Fig. 4) holds chi^2 and the residual of the
+    iterate after iterations 2, 4, 6 of a 2 x 3 schedule (every 2nd and the
+    last), each equal to the diagnostics of that iterate recomputed from a
+    run stopped there."""
+    from oracle.geometry import healpix_grid
+    from oracle.sht import SHT
+    from paper_1801_05358_amd import inputs
+    nside, lmax = 4, 8
+    p = inputs.make_problem(1, nside=nside, lmax=lmax)
+    sht = SHT(healpix_grid(nside), lmax)
+    d = sht.synthesis(inputs.signal_alm(1, lmax, 0)) + inputs.noise_map(1, p["ncov"], p["obs"], 0)
+    r = dm.solve(sht, d, p["ncov"], p["obs"], p["cl"], 1e3, 2, 3, diagnostics_every=2)
+    g = r["diagnostics"]
+    assert g["iteration"] == [2, 4, 6]
+    st = dm.setup(sht.grid, p["ncov"], p["obs"], d)
+    lam = dm.schedule(1e3, 2)
+    for i, c2, rs in zip(g["iteration"], g["chi2"], g["residual"]):
+        counts = [min(i, 3), max(i - 3, 0)]
+        u = dm.messenger_run_counts(sht, st["d0"], st["K"], st["b"], st["tau"], p["cl"], lam, counts)[0]
+        assert abs(c2 - dm.chi2(sht, u, d, p["ncov"], p["obs"], p["cl"])) <= 1e-12 * c2
+        assert abs(rs - dm.residual(sht, u, d, p["ncov"], p["obs"], p["cl"])) <= 1e-12 * rs
+    assert np.array_equal(r["u"], dm.solve(sht, d, p["ncov"], p["obs"], p["cl"], 1e3, 2, 3)["u"])
+    e = dm.solve_eps(sht, d, p["ncov"], p["obs"], p["cl"], 1e3, 0.5, 1e-2, 1e-3, 1.1, 7, diagnostics_every=3)
+    assert e["diagnostics"]["iteration"] == [3, 6, 7]
