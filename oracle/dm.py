@@ -32,7 +32,11 @@ Follows the paper step by step (Kodi Ramanah, Lavaux & Wandelt 2018):
 * constrained realizations, eq 19: s_CR = W(d - d_hat) + s_hat;
 * Appendix A's refinement (modified Jacobi relaxation), in the form that
   carries over to the sphere: corrections s += W~(W Y r) with r the
-  residual of the Wiener filter equation on the range of S (refine()).
+  residual of the Wiener filter equation on the range of S (refine());
+* the hierarchical framework's adaptive working resolution (text after
+  eq 9, Sec. 4): at truncation mu only the scales up to ell_iter(mu) carry
+  signal information, and the transforms of that cooling step run with a
+  band limit a little above it (adaptive= in solve() and solve_eps()).
 """
 
 import numpy as np
@@ -156,6 +160,34 @@ def apply_blocks(F, a, lmax):
     return u
 
 
+# ----------------------------------------------------------------------------
+# adaptive working resolution (text after eq 9; Sec. 4)
+# ----------------------------------------------------------------------------
+def prior_top_eigenvalue(cl):
+    """Largest eigenvalue of each S_l (the TE block and BB), [lmax+1]."""
+    S2, BB = signal_blocks(cl)
+    return np.maximum(np.linalg.eigvalsh(S2)[:, -1], BB)
+
+
+def ell_iter(cl, mu):
+    """The largest l whose prior S_l has an eigenvalue >= mu: above it the
+    prior clamped at mu (the truncation of the text after eq 9) is mu 1 in
+    every field, so the filter is the constant mu / (mu + tau) and carries no
+    signal information; -1 if there is no such l."""
+    top = prior_top_eigenvalue(cl)
+    idx = np.nonzero(top >= mu)[0]
+    return int(idx[-1]) if idx.size else -1
+
+
+def working_lmax(cl, mu, lmax, factor):
+    """Band limit of the transforms at truncation mu: slightly above
+    ell_iter (Sec. 4: the working resolution follows ell_iter with its
+    Nyquist frequency a little higher), L = min(lmax, max(2, ceil(factor
+    ell_iter))) for factor >= 1."""
+    li = ell_iter(cl, mu)
+    return int(min(lmax, max(2, int(np.ceil(factor * li - 1e-9)))))
+
+
 def schedule(lambda0, nsteps):
     """lambda_k = lambda0^(1 - k/(K-1)), k = 0..K-1; the last one is 1."""
     if nsteps <= 1:
@@ -185,18 +217,30 @@ def diagnostics_recorder(sht, d, ncov, obs, cl, every):
     return record, out
 
 
-def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False, diagnostics_every=0):
+def adaptive_lcuts(cl, lambdas, tau, lmax, factor):
+    """Per cooling step the working band limit (working_lmax at mu_k =
+    (lambda_k - 1) tau); factor 0 = the full band throughout."""
+    if not factor:
+        return None
+    return [working_lmax(cl, (lam - 1.0) * tau, lmax, factor) for lam in lambdas]
+
+
+def solve(sht, d, ncov, obs, cl, lambda0, nsteps, iters_per_step, trace=False, diagnostics_every=0,
+          adaptive=0.0):
     """Run the dual messenger loop.  Returns dict(u [3, nalm], ux = Y u
     [3, npix], tau, cauchy (last), trace (list of per-iteration cauchy),
     diagnostics (with diagnostics_every > 0: iteration, chi2, residual
-    lists, see diagnostics_recorder))."""
+    lists, see diagnostics_recorder), lcuts (with adaptive = factor >= 1:
+    the working band limit of each cooling step, adaptive_lcuts))."""
     st = setup(sht.grid, ncov, obs, d)
     record, diag = diagnostics_recorder(sht, d, ncov, obs, cl, diagnostics_every)
     lams = schedule(lambda0, nsteps)
+    lcuts = adaptive_lcuts(cl, lams, st["tau"], sht.lmax, adaptive)
     u, ux, cauchy = messenger_run_counts(sht, st["d0"], st["K"], st["b"], st["tau"], cl, lams,
-                                         [iters_per_step] * len(lams), record=record)
+                                         [iters_per_step] * len(lams), record=record, lcuts=lcuts)
     return dict(u=u, ux=ux, tau=st["tau"], cauchy=cauchy[-1] if cauchy else float("nan"),
-                trace=cauchy if trace else None, setup=st, diagnostics=diag if diagnostics_every > 0 else None)
+                trace=cauchy if trace else None, setup=st, diagnostics=diag if diagnostics_every > 0 else None,
+                lcuts=lcuts)
 
 
 def messenger_run(sht, t, K, b, tau, cl, lambda0, nsteps, iters_per_step):
@@ -207,18 +251,31 @@ def messenger_run(sht, t, K, b, tau, cl, lambda0, nsteps, iters_per_step):
     return messenger_run_counts(sht, t, K, b, tau, cl, lams, [iters_per_step] * len(lams))
 
 
-def messenger_run_counts(sht, t, K, b, tau, cl, lambdas, counts, record=None):
+def band_limited(F, L):
+    """The filter F with its rows above l = L set to zero: u = P_L F t_hat,
+    the harmonic update restricted to the working band limit L."""
+    out = tuple(np.array(f, dtype=float) for f in F)
+    for f in out:
+        f[L + 1:] = 0.0
+    return out
+
+
+def messenger_run_counts(sht, t, K, b, tau, cl, lambdas, counts, record=None, lcuts=None):
     """The same loop with counts[k] iterations at cooling step k (lambda =
     lambdas[k]); record (optional) is called as record(u_i, i, last) after
-    each iteration's harmonic update."""
+    each iteration's harmonic update; lcuts (optional) gives each step's
+    working band limit L_k (band_limited; None or L_k >= lmax: the full
+    band)."""
     lmax = sht.lmax
     u_prev = None
     cauchy = []
     u = ux = None
     total, i = sum(counts), 0
-    for lam, count in zip(lambdas, counts):
+    for k, (lam, count) in enumerate(zip(lambdas, counts)):
         mu = (lam - 1.0) * tau
         F = messenger_filter(cl, mu, tau)
+        if lcuts is not None and lcuts[k] < lmax:
+            F = band_limited(F, lcuts[k])
         for _ in range(count):
             t_hat = sht.analysis(t)
             u = apply_blocks(F, t_hat, lmax)
@@ -255,7 +312,8 @@ def eps_thresholds(nsteps, eps_start, eps_end, eta):
     return eps
 
 
-def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters, diagnostics_every=0):
+def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max_iters, diagnostics_every=0,
+              adaptive=0.0):
     """Algorithm 1 with its stopping rule: at each cooling step repeat the
     iteration until ||u_i - u_{i-1}|| / ||u_i|| < eps_j (u_0 = 0, so every
     step runs at least one iteration), then cool; stop early once max_iters
@@ -270,10 +328,13 @@ def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max
     u_prev = np.zeros((3, lm_arrays(lmax)[0].size), dtype=complex)
     lams = eps_schedule(lambda0, beta)
     eps = eps_thresholds(len(lams), eps_start, eps_end, eta)
+    lcuts = adaptive_lcuts(cl, lams, tau, lmax, adaptive)
     trace, steps = [], []
     u = ux = None
     for j, lam in enumerate(lams):
         F = messenger_filter(cl, (lam - 1.0) * tau, tau)
+        if lcuts is not None and lcuts[j] < lmax:
+            F = band_limited(F, lcuts[j])
         while len(trace) < max_iters:
             t_hat = sht.analysis(t)
             u = apply_blocks(F, t_hat, lmax)
@@ -290,7 +351,7 @@ def solve_eps(sht, d, ncov, obs, cl, lambda0, beta, eps_start, eps_end, eta, max
         if len(trace) >= max_iters:
             break
     return dict(u=u, ux=ux, tau=tau, iterations=len(trace), trace=trace, steps=steps, lambdas=lams, eps=eps,
-                diagnostics=diag if diagnostics_every > 0 else None)
+                diagnostics=diag if diagnostics_every > 0 else None, lcuts=lcuts)
 
 
 # ----------------------------------------------------------------------------
