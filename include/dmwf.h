@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 8
+#define DMWF_ABI_VERSION 9
 
 typedef enum {
     DM_OK = 0,
@@ -215,6 +215,25 @@ dm_status dm_set_schedule(dm_plan* plan, const dm_schedule* schedule);
  * the iteration count; *n = 0 after a fixed-mode solve.  Errors: DM_EINVAL
  * for a null plan or n.                                                    */
 dm_status dm_schedule_trace(const dm_plan* plan, double* cauchy, int* step, int cap, int* n);
+
+/* Adaptive working resolution (the hierarchical framework of the text
+ * after eq 9 and the working-resolution proposal of Sec. 4).  At cooling
+ * step k, with mu_k = (lambda_k - 1) tau, the prior clamped at mu_k is mu_k 1
+ * in T, E and B above ell_iter(mu_k), the largest l whose S_l (the TE block
+ * and BB) has an eigenvalue >= mu_k; the step then runs its harmonic update
+ * with the band limit L_k = min(lmax, max(2, ceil(factor ell_iter(mu_k)))):
+ * u = P_L F t_hat, coefficients above L_k set to zero, and the transforms
+ * skip the degrees and orders above L_k.  The pixel grid, K and b stay those
+ * of the data.  The last step (mu = 0) always runs the full band.  factor
+ * 0 (the default) turns it off, factor >= 1 turns it on for later Wiener
+ * filter solves (not dm_iterate); other values are DM_EINVAL.            */
+dm_status dm_set_adaptive_resolution(dm_plan* plan, double factor);
+
+/* Band limit L_k of each cooling step of the last solve's schedule (lmax
+ * for every step when adaptive resolution is off).  Copies min(cap, n)
+ * values to the caller's host array (NULL allowed), sets *n to the number
+ * of cooling steps.  Errors: DM_EINVAL for a null plan or n.              */
+dm_status dm_step_band_limits(const dm_plan* plan, int* lcut, int cap, int* n);
 
 /* Diagnostics trace (Fig. 4's chi^2 and residual panels): with every > 0,
  * every later Wiener filter solve evaluates, for the iterate u_i after

@@ -261,6 +261,20 @@ void alm2map_dev(dm_plan* p, int nrhs, const double* alm, double* map, hipStream
     ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, s);
 }
 
+// the band limit of the transforms launched in a scope (adaptive working
+// resolution: a cooling step's limit; 0 = the full band)
+struct LcutScope {
+    dm_plan* p;
+    int saved;
+    LcutScope(dm_plan* p_, int lcut) : p(p_), saved(p_->lcut) { p->lcut = lcut; }
+    ~LcutScope() { p->lcut = saved; }
+};
+
+// band limit of cooling step k of the prepared schedule
+int step_lcut(const dm_plan* p, int64_t k) {
+    return (k >= 0 && k < (int64_t)p->step_lcut.size()) ? p->step_lcut[k] : 0;
+}
+
 // runs the transforms of a scope in another precision (the mixed plan's
 // FP64 epilogue: the returned map and the residual)
 struct PrecisionScope {
@@ -275,8 +289,34 @@ void check_rhs(dm_plan* p, int nrhs) {
             "nrhs must be in [1, max_rhs=" + std::to_string(p->max_rhs) + "]");
 }
 
-// upload all cooling-step filters [nsteps][lmax+1][4] for the schedule
-void prepare_filters(dm_plan* p, const std::vector<double>& lambdas) {
+// The largest l whose prior S_l has an eigenvalue >= mu (-1 if none): above
+// it the prior clamped at mu is mu 1 in every field (the truncation of the
+// text after eq 9), and the filter carries no signal information.
+int ell_iter(const dm_plan* p, double mu) {
+    const int L = p->lmax + 1;
+    for (int l = p->lmax; l >= 0; --l) {
+        const double tt = p->cl[l], ee = p->cl[L + l], bb = p->cl[2 * L + l], te = p->cl[3 * L + l];
+        const double h = 0.5 * (tt - ee);
+        const double top = std::max(0.5 * (tt + ee) + std::sqrt(h * h + te * te), bb);
+        if (top >= mu) return l;
+    }
+    return -1;
+}
+
+// Working band limit of a cooling step (Sec. 4: the working resolution
+// follows ell_iter with its Nyquist frequency a little above it):
+// min(lmax, max(2, ceil(factor ell_iter))); lmax when adaptive resolution is off.
+int working_lmax(const dm_plan* p, double mu, double factor) {
+    if (!(factor >= 1.0)) return p->lmax;
+    const int li = ell_iter(p, mu);
+    const double c = std::ceil(factor * li - 1e-9);
+    return (int)std::min<double>(p->lmax, std::max(2.0, c));
+}
+
+// upload all cooling-step filters [nsteps][lmax+1][4] for the schedule; with
+// `adaptive`, each step's rows above its working band limit are zero (the
+// harmonic update u = P_L F t_hat) and the limits go to p->step_lcut
+void prepare_filters(dm_plan* p, const std::vector<double>& lambdas, bool adaptive = false) {
     const size_t per = (size_t)(p->lmax + 1) * 4;
     const size_t need = per * lambdas.size();
     if ((int)lambdas.size() > p->filters_cap) {
@@ -291,8 +331,15 @@ void prepare_filters(dm_plan* p, const std::vector<double>& lambdas) {
         p->h_pinned_len = need;
     }
     std::vector<double> F;
+    p->step_lcut.assign(lambdas.size(), p->lmax);
     for (size_t k = 0; k < lambdas.size(); ++k) {
-        build_filter(p->cl, p->lmax, (lambdas[k] - 1.0) * p->tau, p->tau, F);
+        const double mu = (lambdas[k] - 1.0) * p->tau;
+        build_filter(p->cl, p->lmax, mu, p->tau, F);
+        if (adaptive) {
+            const int L = working_lmax(p, mu, p->adaptive);
+            p->step_lcut[k] = L;
+            for (size_t i = (size_t)(L + 1) * 4; i < per; ++i) F[i] = 0.0;
+        }
         std::memcpy(p->h_pinned + k * per, F.data(), per * sizeof(double));
     }
     HIPCHK(hipMemcpyAsync(p->d_filters, p->h_pinned, need * sizeof(double), hipMemcpyHostToDevice, p->stream));
@@ -351,6 +398,7 @@ void messenger_step(dm_plan* p, int nrhs, double* t_out, hipStream_t s);
 // synthesis, where the map and ring buffers they use hold nothing live.
 void diag_prepare(dm_plan* p, int nrhs, hipStream_t s) {
     PrecisionScope fp64(p, DM_FP64);
+    LcutScope full(p, 0);
     HIPCHK(hipMemsetAsync(p->d_ux, 0, (size_t)nrhs * 3 * p->npix * sizeof(double), s));
     HIPCHK(launch_residual_maps(p, nrhs, p->d_ux, p->d_d0, nullptr, p->d_red + 64, s));
     map2alm_dev(p, nrhs, p->d_ux, p->d_alm_y, false, s);
@@ -358,6 +406,7 @@ void diag_prepare(dm_plan* p, int nrhs, hipStream_t s) {
 
 void diag_record(dm_plan* p, int nrhs, const double* alm, int64_t iter, hipStream_t s) {
     PrecisionScope fp64(p, DM_FP64);
+    LcutScope full(p, 0);
     alm2map_dev(p, nrhs, alm, p->d_ux, s);
     double* chi = p->d_red + 64;
     HIPCHK(launch_residual_maps(p, nrhs, p->d_ux, p->d_d0, nullptr, chi, s));
@@ -476,6 +525,7 @@ void fixed_loop(dm_plan* p, int nrhs, double* alm, int64_t from, int64_t end, hi
     for (int64_t it = from; it < end;) {
         const int64_t k = it / niter;
         const double* F = p->d_filters + per * k;
+        LcutScope band(p, step_lcut(p, k));
         // this cooling step's iterations before the solve's last one
         const int64_t stop = std::min<int64_t>((k + 1) * niter, end - 1);
         if (it < stop) {
@@ -506,6 +556,7 @@ void counted_loop(dm_plan* p, int nrhs, double* alm, const std::vector<int>& cou
     for (size_t k = 0; k < counts.size(); ++k) {
         if (counts[k] <= 0) continue;
         const double* F = p->d_filters + per * k;
+        LcutScope band(p, step_lcut(p, (int64_t)k));
         const bool last_step = done + counts[k] == total;
         const int run = last_step ? counts[k] - 1 : counts[k];
         run_iterations(p, nrhs, F, alm, run, s, graphs);
@@ -630,7 +681,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         resumable = false;
     }
     const std::vector<double> lam = schedule_lambdas(p->sched);
-    prepare_filters(p, lam);
+    prepare_filters(p, lam, p->adaptive >= 1.0);
     sync_plan_stream_to(p, s);
     const size_t per = (size_t)(p->lmax + 1) * 4;
     const int64_t alm_len = (int64_t)nrhs * 3 * p->nalm * 2;
@@ -733,6 +784,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
         next_step = k0;
         for (int k = k0; k < nsteps && !done; ++k) {
             const double* F = p->d_filters + per * k;
+            LcutScope band(p, step_lcut(p, k));
             const double thr = (k == nsteps - 1) ? sc.eps_end
                                                  : std::max(sc.eps_end, sc.eps_start * std::pow(sc.eps_eta, -(double)k));
             for (;;) {
@@ -1549,6 +1601,23 @@ dm_status dm_refinement_trace(const dm_plan* p, double* history, int cap, int* n
     if (history) std::copy(p->refine_hist.begin(), p->refine_hist.begin() + k, history);
     *n = cnt;
     if (nrhs) *nrhs = cnt ? p->refine_nrhs : 0;
+    return DM_OK;
+}
+
+dm_status dm_set_adaptive_resolution(dm_plan* p, double factor) {
+    return guarded(p, [&] {
+        REQUIRE(factor == 0.0 || (std::isfinite(factor) && factor >= 1.0), DM_EINVAL,
+                "factor must be 0 (off) or >= 1");
+        p->adaptive = factor;
+    });
+}
+
+dm_status dm_step_band_limits(const dm_plan* p, int* lcut, int cap, int* n) {
+    if (!p || !n) return DM_EINVAL;
+    const int cnt = (int)p->step_lcut.size();
+    const int k = std::max(0, std::min(cap, cnt));
+    if (lcut) std::copy(p->step_lcut.begin(), p->step_lcut.begin() + k, lcut);
+    *n = cnt;
     return DM_OK;
 }
 

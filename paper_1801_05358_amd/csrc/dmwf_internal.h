@@ -188,6 +188,12 @@ struct dm_plan {
     int refine_best = 0;               // 0: the last iterate (Appendix A), 1: the one of smallest residual
     std::vector<int> refine_chosen;    // [nrhs] index in refine_hist of the returned iterate
 
+    // adaptive working resolution: factor (0 = off) and the band limit of
+    // each cooling step of the last prepared schedule
+    double adaptive = 0.0;
+    std::vector<int> step_lcut;
+    int lcut = 0;                      // band limit of the transforms being launched (lmax: full)
+
     // diagnostics trace (Fig. 4): chi^2 (eq 3) and the Appendix C residual
     // of the iterate after every diag_every-th iteration and after the last;
     // [entries][nrhs] per quantity, the iteration of each entry

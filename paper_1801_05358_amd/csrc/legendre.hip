@@ -47,6 +47,7 @@ __device__ __forceinline__ int wave_max(int v) {
 
 struct LegArgs {
     int lmax, mmax, npairs;
+    int lend;             // band limit of this launch: degrees and orders above it are skipped
     int64_t nalm;
     const double* __restrict__ pair_x;
     const double* __restrict__ coef;    // scaled recursions, [nalm][kCoefSStride]
@@ -68,6 +69,7 @@ LegArgs leg_args(dm_plan* p) {
     a.lstart = p->d_lstart;
     a.seed = p->d_seed;
     a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
+    a.lend = (p->lcut > 0 && p->lcut < p->lmax) ? p->lcut : p->lmax;
     return a;
 }
 
@@ -255,6 +257,7 @@ __global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2
     const int m = blockIdx.y;
     const int rhs = blockIdx.z;
     const int lmax = A.lmax;
+    const int lend = A.lend;          // degrees above it contribute nothing (zero coefficients)
     const int64_t base = mbase(m, lmax);
     const double2* __restrict__ aT = alm + (int64_t)rhs * 3 * A.nalm + base;
     const double2* __restrict__ aP = aT + A.nalm;
@@ -276,26 +279,26 @@ __global__ __launch_bounds__(256) void leg_synth_kernel(LegArgs A, const double2
     if (m < 2) hi = max(hi, 2);
 
     int l = lo;
-    if (l <= lmax) {
+    if (l <= lend) {
         // activation phase: some lanes start their recursion at l
         if ((l + m) & 1) synth_step<R, 1, false, true>(A, m, l, cf, aT, aP, aM, S, acc);
         else synth_step<R, 0, false, true>(A, m, l, cf, aT, aP, aM, S, acc);
         ++l;
-        const int h = min(hi, lmax);
+        const int h = min(hi, lend);
         for (; l <= h; ++l) {
             if ((l + m) & 1) synth_step<R, 1, true, true>(A, m, l, cf, aT, aP, aM, S, acc);
             else synth_step<R, 0, true, true>(A, m, l, cf, aT, aP, aM, S, acc);
         }
         // steady state: every lane active, parity unrolled
-        if (l <= lmax && ((l + m) & 1)) {
+        if (l <= lend && ((l + m) & 1)) {
             synth_step<R, 1, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
             ++l;
         }
-        for (; l + 1 <= lmax; l += 2) {
+        for (; l + 1 <= lend; l += 2) {
             synth_step<R, 0, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
             synth_step<R, 1, true, false>(A, m, l + 1, cf, aT, aP, aM, S, acc);
         }
-        if (l <= lmax) synth_step<R, 0, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
+        if (l <= lend) synth_step<R, 0, true, false>(A, m, l, cf, aT, aP, aM, S, acc);
     }
 
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
@@ -420,6 +423,9 @@ __global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, co
     const int rhs = blockIdx.z;
     const int nrhs = gridDim.z;
     const int lmax = A.lmax;
+    const int lend = A.lend;
+    // orders above the band limit: nothing to sum (the combine writes zeros)
+    if (m > lend) return;
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefSStride;
     const int lane = threadIdx.x & 63;
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, co
 
     double* out = partial + ((((int64_t)wave * nrhs + rhs) * 3) * A.nalm) * 2;
     // degrees below the wave's first active one get zero partial sums
-    const int lz = min(lo, lmax + 1);
+    const int lz = min(lo, lend + 1);
     for (int q = lane; q < (lz - m) * 6; q += 64) {
         const int l = m + q / 6, k = q % 6;
         out[((int64_t)(k >> 1) * A.nalm + base + l) * 2 + (k & 1)] = 0.0;
@@ -470,8 +476,8 @@ __global__ __launch_bounds__(kAnaThreads) void leg_analysis_kernel(LegArgs A, co
 
     // reduction roles: 2 lanes per (degree, component) row
     const int o = lane >> 1, q = lane & 1;
-    for (int lc = lo; lc <= lmax; lc += kAnaL) {
-        const int ln = min(kAnaL, lmax + 1 - lc);
+    for (int lc = lo; lc <= lend; lc += kAnaL) {
+        const int ln = min(kAnaL, lend + 1 - lc);
         if (ln == kAnaL && lc > hi) {
             if ((lc + m) & 1) ana_round<R, 1>(A, m, lc, cf, S, D, tile, lane);
             else ana_round<R, 0>(A, m, lc, cf, S, D, tile, lane);
@@ -572,7 +578,7 @@ __global__ __launch_bounds__(256) void cauchy_reduce_kernel(const double* __rest
 // multiplied by S, and so is the spin-basis copy (the batched synthesis
 // contracts the scaled functions with it).
 template <typename PV>
-__global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, int nchunks, int nrhs,
+__global__ __launch_bounds__(256) void combine_kernel(int lmax, int lend, int64_t nalm, int nchunks, int nrhs,
                                                       const PV* __restrict__ partial,
                                                       const double* __restrict__ filt, double2* __restrict__ alm,
                                                       double2* __restrict__ spin, double* __restrict__ cpart,
@@ -584,10 +590,12 @@ __global__ __launch_bounds__(256) void combine_kernel(int lmax, int64_t nalm, in
     if (l <= lmax) {
         const int64_t idx = mbase(m, lmax) + l;
         double2 a[3];
+        // above the band limit the analysis wrote nothing: the coefficient is 0
+        const int nc = (l <= lend && m <= lend) ? nchunks : 0;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             double2 s = make_double2(0.0, 0.0);
-            for (int c = 0; c < nchunks; ++c) {
+            for (int c = 0; c < nc; ++c) {
                 const PV v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
                 s.x += (double)v.x;
                 s.y += (double)v.y;
@@ -711,12 +719,13 @@ hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partia
                           const double* filter, double* alm, double* spin, double* cpart, const double* scale,
                           hipStream_t s) {
     dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
+    const int lend = (p->lcut > 0 && p->lcut < p->lmax) ? p->lcut : p->lmax;
     if (partial32)
-        hipLaunchKernelGGL(combine_kernel<float2>, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
+        hipLaunchKernelGGL(combine_kernel<float2>, grid, dim3(256), 0, s, p->lmax, lend, p->nalm, nslots, nrhs,
                            reinterpret_cast<const float2*>(partial), filter, reinterpret_cast<double2*>(alm),
                            reinterpret_cast<double2*>(spin), cpart, scale);
     else
-        hipLaunchKernelGGL(combine_kernel<double2>, grid, dim3(256), 0, s, p->lmax, p->nalm, nslots, nrhs,
+        hipLaunchKernelGGL(combine_kernel<double2>, grid, dim3(256), 0, s, p->lmax, lend, p->nalm, nslots, nrhs,
                            reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
                            reinterpret_cast<double2*>(spin), cpart, scale);
     return hipGetLastError();

