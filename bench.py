@@ -46,8 +46,13 @@ PEAK = {   # dense vendor peaks, TFLOP/s
 HBM_PEAK = 8000.0                                         # GB/s
 ACC_GATE = 1e-5
 COPY_BYTES = 1 << 30                                      # calibration copy for the traffic counters
-TRAFFIC_KERNELS = {"legendre_analysis": "bana_kernel", "legendre_synthesis": "bsyn_kernel"}
-KERNEL_SOURCES = {"legendre_analysis": "legendre_mfma.hip", "legendre_synthesis": "legendre_mfma.hip"}
+# kernel class -> (name key, dispatches per step): the ring step of the
+# 8-RHS workload at Nside 1024 runs as two launches of the same kernel (the
+# large and the small transforms), summed per step
+TRAFFIC_KERNELS = {"legendre_analysis": ("bana_kernel", 1), "legendre_synthesis": ("bsyn_kernel", 1),
+                   "ring_fft_pointwise": ("ring_kernel<3", 2)}
+KERNEL_SOURCES = {"legendre_analysis": "legendre_mfma.hip", "legendre_synthesis": "legendre_mfma.hip",
+                  "ring_fft_pointwise": "ringfft.hip"}
 
 
 def legendre_flops(npairs, nalm, nrhs):
@@ -109,10 +114,11 @@ def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command, last):
         return acc
     fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
 
-    def find(acc, key):
+    def find(acc, key, per):
         for name, d in acc.items():
             if key in name:
-                return [v for _, v in sorted(d.items(), key=lambda kv: int(kv[0]))][-last:]
+                v = [x for _, x in sorted(d.items(), key=lambda kv: int(kv[0]))][-last * per:]
+                return [sum(v[i:i + per]) for i in range(0, len(v) - per + 1, per)]
         return []
 
     def copy_factor(path, counter):
@@ -126,15 +132,16 @@ def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command, last):
         return COPY_BYTES / val if val > 0 else None
 
     ff, fw = copy_factor(fetch_csv, "FETCH_SIZE"), copy_factor(write_csv, "WRITE_SIZE")
-    for kernel, key in TRAFFIC_KERNELS.items():
-        f, w = find(fetch, key), find(write, key)
+    for kernel, (key, per) in TRAFFIC_KERNELS.items():
+        f, w = find(fetch, key, per), find(write, key, per)
         if not f or not w or ff is None or fw is None:
             print(f"no counters for {kernel}", file=sys.stderr)
             continue
         fb = sum(f) / len(f) * ff
         wb = sum(w) / len(w) * fw
         with open(traffic_file(kernel, prec, nrhs), "w") as out:
-            out.write(f"# HBM traffic per launch of {kernel} ({key}), Nside 1024, lmax 2048, {prec}, B = {nrhs}\n")
+            out.write(f"# HBM traffic per launch of {kernel} ({key}, {per} dispatch(es) per step summed), "
+                      f"Nside 1024, lmax 2048, {prec}, B = {nrhs}\n")
             out.write(f"# from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of:\n#   {command}\n")
             out.write(f"# counters scaled by a {COPY_BYTES} B device copy: fetch x{ff:.4f}, write x{fw:.4f}\n")
             out.write(f"source_sha256_16: {source_sha(kernel)}\n")
@@ -143,6 +150,56 @@ def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command, last):
             out.write(f"write_bytes_per_launch: {wb:.6e}\n")
             out.write(f"bytes_per_launch: {fb + wb:.6e}\n")
         print(f"{kernel}: fetch {fb / 1e9:.3f} GB, write {wb / 1e9:.3f} GB per launch")
+
+
+COUNTER_KERNELS = ("bana_kernel", "bsyn_kernel", "ring_kernel", "combine_kernel", "leg_analysis_kernel",
+                   "leg_synth_kernel")
+
+
+def counter_summary(csv_paths, out, command, title, last):
+    """Per-kernel counter summary from rocprofv3 --pmc runs (one CSV per
+    pass): each counter's value per dispatch (summed over the rows of that
+    dispatch), averaged over each kernel's last ``last`` dispatches, for the
+    transform kernels; then derived figures where their counters are there:
+    MFMA FLOP (the MOPS counters count 512 FLOP each), the MFMA pipe's busy
+    fraction (busy cycles per SIMD over the GPU-active cycles times the 1024
+    SIMDs), VALU and LDS instructions per MFMA instruction."""
+    def short(n):
+        n = re.sub(r"dmwf::\(anonymous namespace\)::", "", n)
+        return re.sub(r"\(.*$", "", n)[:60]
+    vals = {}
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            k = short(r["Kernel_Name"])
+            if not any(c in k for c in COUNTER_KERNELS):
+                continue
+            d = vals.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+            d[int(r["Dispatch_Id"])] = d.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+    lines = [f"# {title}", f"# command (one run per pass): {command}",
+             f"# per kernel: counter averages over its last {last} dispatches"]
+    for k in sorted(vals):
+        avg = {}
+        for c, d in sorted(vals[k].items()):
+            v = [x for _, x in sorted(d.items())][-last:]
+            avg[c] = sum(v) / len(v)
+        lines.append("")
+        lines.append(f"[{k}]")
+        for c, v in avg.items():
+            lines.append(f"{c}: {v:.6e}")
+        if "SQ_INSTS_VALU_MFMA_MOPS_F32" in avg or "SQ_INSTS_VALU_MFMA_MOPS_F64" in avg:
+            fl = 512.0 * (avg.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) + avg.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0))
+            lines.append(f"derived_mfma_flop: {fl:.6e}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and avg.get("GRBM_GUI_ACTIVE"):
+            lines.append(f"derived_mfma_busy_frac: "
+                         f"{avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (avg['GRBM_GUI_ACTIVE'] * 1024):.4f}")
+        mf = avg.get("SQ_INSTS_MFMA") or (avg.get("SQ_INSTS_VALU_MFMA_F32", 0.0) + avg.get("SQ_INSTS_VALU_MFMA_F64", 0.0))
+        if mf:
+            if "SQ_INSTS_VALU" in avg:
+                lines.append(f"derived_valu_per_mfma: {(avg['SQ_INSTS_VALU'] - mf) / mf:.3f}")
+            if "SQ_INSTS_LDS" in avg:
+                lines.append(f"derived_lds_per_mfma: {avg['SQ_INSTS_LDS'] / mf:.3f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def kernel_summary(stats_csv, trace_csv, out, command, title, last):
@@ -177,27 +234,82 @@ def kernel_summary(stats_csv, trace_csv, out, command, title, last):
     print("\n".join(lines))
 
 
-def cpu_baseline(lmax, nside, alm):
-    """Time the CPU FP64 oracle on a bounded sample of the same transform:
-    synthesis of a few rings spread over the sphere, scaled to all rings and
-    doubled for the analysis of one iteration (per RHS)."""
+_CPU_WORK = {}      # the CPU baseline's inputs, inherited by forked workers
+
+
+def _oracle_rings(rings):
+    """One worker's share of the CPU baseline: the oracle's synthesis of alm
+    on the given rings and its adjoint (the analysis without weights, whose
+    cost is the same) summed over the same rings, with one BLAS thread.
+    Returns the seconds taken."""
+    lmax, nside, alm, maps = (_CPU_WORK[k] for k in ("lmax", "nside", "alm", "maps"))
     from threadpoolctl import threadpool_limits
     from oracle.geometry import healpix_grid
     from oracle.sht import SHT
-    grid = healpix_grid(nside)
-    nr = len(grid["theta"])
-    # 24 rings spread from pole to pole (polar caps and equatorial belt)
-    sample = sorted(set(int(round(v)) for v in [i * (nr - 1) / 23.0 for i in range(24)]))
     with threadpool_limits(limits=1):
-        sht = SHT(grid, lmax, cache_bytes=0)
+        sht = SHT(healpix_grid(nside), lmax, cache_bytes=0)
         t0 = time.perf_counter()
-        sht.synthesis(alm, rings=sample)
-        dt = time.perf_counter() - t0
-    per_iter = 2.0 * dt * nr / len(sample)
-    return {"value": 1.0 / per_iter, "unit": "RHS-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle synthesis of {len(sample)} of {nr} rings at Nside {nside}, lmax {lmax} "
-                      f"({dt:.1f} s), scaled by {nr}/{len(sample)} rings and x2 for the analysis of one "
-                      f"iteration of one RHS; NumPy FP64, BLAS limited to 1 thread"}
+        sht.synthesis(alm, rings=rings)
+        sht.adjoint(maps, rings=rings)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(lmax, nside, alm, maps, cl, K, b, tau, per_core=6, max_workers=16):
+    """The CPU FP64 oracle on a bounded sample of one iteration of the same
+    workload (one RHS): the transforms (synthesis and adjoint) on a sample
+    of rings spread from pole to pole, scaled to all rings, plus the
+    harmonic update and the pixel update over the whole map, timed once.
+    Single core: per_core rings in one process.  All cores: a pool of
+    min(max_workers, cpu count) processes, each with one BLAS thread, on
+    per_core rings each (the oracle's transforms are sums over rings, so
+    the rings split over processes); the iteration estimate is the pool's
+    wall time scaled by all rings over the rings it did."""
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import dm
+    from oracle.geometry import healpix_grid
+    nr = 4 * nside - 1
+    nw = max(1, min(max_workers, os.cpu_count() or 1))
+
+    def spread(count, offset=0.0):
+        return sorted(set(int(round((i + offset) * (nr - 1) / max(count - 1, 1))) for i in range(count)))
+
+    one = spread(per_core)
+    # the pointwise parts of an iteration (eq 8's filter, eq 9's update) over everything
+    with threadpool_limits(limits=1):
+        grid = healpix_grid(nside)
+        F = dm.messenger_filter(cl, 10.0 * tau, tau)
+        t0 = time.perf_counter()
+        dm.apply_blocks(F, alm, lmax)
+        dm.pix_apply(K, maps) + b
+        t_point = time.perf_counter() - t0
+    _CPU_WORK.update(lmax=lmax, nside=nside, alm=alm, maps=maps)
+    t1 = _oracle_rings(one)
+    single = t1 * nr / len(one) + t_point
+    # all cores: every worker a sample of its own
+    samples = [spread(per_core, (w + 0.5) / nw) for w in range(nw)]
+    samples = [[min(r, nr - 1) for r in sm] for sm in samples]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(nw) as pool:
+        pool.map(_oracle_rings, samples, chunksize=1)
+    wall = time.perf_counter() - t0
+    done = sum(len(sm) for sm in samples)
+    multi = wall * nr / done + t_point
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": 1.0 / multi, "unit": "RHS-iterations/s", "cores": nw, "kind": "oracle",
+            "single_core_value": 1.0 / single, "nproc": os.cpu_count(), "cpu_model": model,
+            "sample": f"one oracle iteration at Nside {nside}, lmax {lmax} (one RHS): synthesis and adjoint "
+                      f"transforms timed on {len(one)} rings spread pole to pole ({t1:.1f} s on one core) and, "
+                      f"with {nw} processes of one BLAS thread each, on {done} rings ({wall:.1f} s wall), "
+                      f"scaled to all {nr} rings, plus the filter and pixel update over the whole map "
+                      f"({t_point:.1f} s); NumPy FP64, full m range, no symmetry"}
 
 
 def field_errors(x, ref, nalm, lmax):
@@ -296,6 +408,8 @@ def main():
                     help="dispatches per kernel that count (the timed and the profiled run of --steps 3)")
     ap.add_argument("--kernel-summary", nargs=3, metavar=("STATS_CSV", "TRACE_CSV", "OUT"),
                     help="write a kernel-time summary from a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV_OR_OUT",
+                    help="write a per-kernel counter summary: the --pmc CSV files of the passes, then OUT")
     ap.add_argument("--summary-title", default="")
     ap.add_argument("--summary-last", type=int, default=20,
                     help="dispatches per kernel averaged from the trace (the profiled run of --steps 20)")
@@ -306,6 +420,10 @@ def main():
         return
     if args.kernel_summary:
         kernel_summary(*args.kernel_summary, args.traffic_command, args.summary_title, args.summary_last)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary[:-1], args.counter_summary[-1], args.traffic_command,
+                        args.summary_title, args.summary_last)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU "
@@ -410,7 +528,10 @@ def main():
     else:
         bound, peak = "alu", PEAK["fp64_valu"]
     traffic = read_traffic(dom, args.precision, B) if (cfg, nside, lmax, corr) == (3, 1024, 2048, False) else None
+    wk = plan.transform_work()
     ring_ms, ring_n = kt["ring_fft_pointwise"]
+    ring_traffic = (read_traffic("ring_fft_pointwise", args.precision, B)
+                    if (cfg, nside, lmax, corr) == (3, 1024, 2048, False) else None)
     # the mixed path keeps the ring Fourier data in FP32 when the batched
     # matrix-core kernels run (from 2 RHS on); K and b stay FP64
     rb = ring_bytes(plan.npix, plan.nrings, lmax, B, p_ring=4 if (args.precision == "mixed" and B >= 2) else 8)
@@ -439,11 +560,17 @@ def main():
         "rhs_iterations_per_s": round(B * its, 3),
         "roofline": {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # the points at or above their start degrees, where the
+                     # kernels run the recursion and contraction
+                     "executed_points_ratio": round(wk[1] / wk[0], 4),
+                     "executed_frac": round(achieved * wk[1] / wk[0] / peak, 4)},
         "kernels_ms_avg": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
-        "autotune": {"syn_mchunk": tune["syn_mchunk"], "ana_mchunk": tune["ana_mchunk"]},
+        "autotune": {k: tune[k] for k in ("syn_mchunk", "ana_mchunk", "syn_waves", "ring_big_threads",
+                                          "ring_small_threads")},
         "ring_fft_hbm": {"achieved": round(rb / (ring_ms / max(ring_n, 1) * 1e-3) / 1e9, 1), "peak": HBM_PEAK,
-                         "unit": "GB/s"},
+                         "unit": "GB/s", "frac": round(rb / (ring_ms / max(ring_n, 1) * 1e-3) / 1e9 / HBM_PEAK, 4),
+                         "algorithmic_bytes": rb, "traffic": ring_traffic},
     }
 
     if args.refine > 0:
@@ -518,7 +645,10 @@ def main():
         del src, dst
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
-        rec["cpu_baseline"] = cpu_baseline(lmax, nside, s[0])
+        from oracle import dm
+        from oracle.geometry import healpix_grid
+        st = dm.setup(healpix_grid(nside), ncov, obs, inputs.noise_map(cfg, ncov, obs, 0))
+        rec["cpu_baseline"] = cpu_baseline(lmax, nside, s[0], st["d0"], prob["cl"], st["K"], st["b"], st["tau"])
     print(json.dumps(rec), flush=True)
 
 

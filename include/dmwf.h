@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define DMWF_ABI_VERSION 9
+#define DMWF_ABI_VERSION 11
 
 typedef enum {
     DM_OK = 0,
@@ -151,6 +151,8 @@ int dm_device_count(void);
  * result beyond FP rounding except DMWF_RING_FP32:
  *   DMWF_MFMA=0|1          batched matrix-core Legendre kernels off / on
  *   DMWF_SYN_MCHUNK, DMWF_ANA_MCHUNK   their m-chunk per XCD (see dm_autotune)
+ *   DMWF_SYN_WAVES=2|4|8   waves per block of the batched synthesis
+ *   DMWF_RING_BIG_THREADS, DMWF_RING_SMALL_THREADS   ring size-class widths
  *   DMWF_SYN_THREADS, DMWF_SYN_R, DMWF_ANA_R   single-RHS kernel tiling
  *   DMWF_GRAPHS=0          fixed-schedule steps launched directly, not as graphs
  *   DMWF_RING_THREADS=256|512|1024     whole-ring workgroup width
@@ -407,21 +409,38 @@ dm_status dm_iterate(dm_plan* plan, int nrhs, const double* d, const double* t_i
 dm_status dm_checkpoint_save(const dm_plan* plan, const char* path);
 dm_status dm_checkpoint_load(dm_plan* plan, const char* path);
 
-/* Autotuner of the batched matrix-core Legendre kernels: for nrhs right-hand
- * sides (a count that uses them: from 2 on for DM_MIXED, 8 for DM_FP64)
- * it times each kernel with every candidate m-chunk (how many consecutive m
- * a chunk of workgroups on one XCD covers: 0, 1, 2, 4, 8) on the plan's own
- * buffers and keeps the fastest for this plan.  The choice changes only
- * which XCD runs which workgroup, never the arithmetic: results stay the
- * same to the last bit.  chunks (nullable, [2]) receives the synthesis and
- * analysis m-chunk, ms (nullable, [2]) their times per launch (0 when the
- * choice came from the cache).  With the environment variable
- * DMWF_TUNE_CACHE naming a file, choices are looked up there first (key:
- * grid, lmax, precision, nrhs column tiles) and new ones appended.  Leaves
- * the plan unchanged (DM_OK, chunks = current values, ms = 0) when nrhs does
- * not use the batched kernels.  Call between solves; it overwrites the
- * plan's transform work buffers.                                          */
-dm_status dm_autotune(dm_plan* plan, int nrhs, int* chunks, double* ms);
+/* Autotuner of the launch shapes of a solve with nrhs right-hand sides,
+ * timed on the plan's own buffers, keeping the fastest for this plan:
+ *  - batched matrix-core Legendre kernels (from 2 RHS on for DM_MIXED, 8
+ *    for DM_FP64): the synthesis' waves per block (2, 4, 8) together with
+ *    its m-chunk, and the analysis' m-chunk (how many consecutive m a chunk
+ *    of workgroups on one XCD covers: 0, 1, 2, 4, 8).  These only move work
+ *    between waves, workgroups and XCDs: results stay the same to the last
+ *    bit;
+ *  - the ring step's two launches by transform size (from 4 RHS on, where
+ *    the plan has both size classes): workgroup widths of the large (512,
+ *    1024) and the small transforms (256, 512, 1024).  A width changes the
+ *    order of a few first-pixel rotation products: results move by FP64
+ *    rounding only.
+ * choice (nullable, [5]) receives the synthesis m-chunk, the analysis
+ * m-chunk, the synthesis waves, the large and the small ring widths; ms
+ * (nullable, [3]) the best synthesis, analysis and ring-step times per
+ * launch (0 for a part not tuned or when the choice came from the cache).
+ * With the environment variable DMWF_TUNE_CACHE naming a file, choices are
+ * looked up there first (key: grid, lmax, precision, column tiles of 8 RHS,
+ * ring classes) and new ones appended.  Leaves the plan unchanged (DM_OK,
+ * choice = current values, ms = 0) when nrhs uses neither.  Call between
+ * solves; it overwrites the plan's transform work buffers.               */
+dm_status dm_autotune(dm_plan* plan, int nrhs, int* choice, double* ms);
+
+/* Work of one Legendre transform of this plan, per right-hand side:
+ * *points = ring pairs x nalm, the (l, m, ring pair) points of the
+ * separable transform, and *executed = the points at or above each
+ * (m, ring pair)'s start degree (below it the associated Legendre functions
+ * are under 2^-100 of their scale and the recursion and contraction skip
+ * them; the seeds fix it when the plan is made).  Errors: DM_EINVAL for a
+ * null argument.                                                          */
+dm_status dm_transform_work(dm_plan* plan, int64_t* points, int64_t* executed);
 
 /* Per-kernel GPU timing, measured with HIP events on the plan's stream
  * when enabled: enable != 0 turns recording on and clears the totals.

@@ -168,13 +168,16 @@ class SHT:
         return out
 
     # -- adjoint -----------------------------------------------------------
-    def adjoint(self, maps):
-        """Y^T: maps [3, npix] (I, Q, U) -> alm [3, nalm] (T, E, B)."""
+    def adjoint(self, maps, rings=None):
+        """Y^T: maps [3, npix] (I, Q, U) -> alm [3, nalm] (T, E, B).  With
+        ``rings`` given, only those rings' terms of the sum (a partial sum,
+        for sampled evaluation)."""
         lmax, g = self.lmax, self.grid
         aT = np.zeros((lmax + 1, self.ms.size), dtype=np.complex128)
         a2p = np.zeros_like(aT)
         a2m = np.zeros_like(aT)
-        for rr, (l0, l2p, l2m) in self._chunks(np.arange(len(g["theta"]))):
+        rings = np.arange(len(g["theta"])) if rings is None else np.asarray(rings)
+        for rr, (l0, l2p, l2m) in self._chunks(rings):
             GT = np.empty((rr.size, self.ms.size), dtype=np.complex128)
             GP = np.empty_like(GT)
             GM = np.empty_like(GT)

@@ -1031,6 +1031,11 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         {
             const int rt = env_int("DMWF_RING_THREADS", 0);
             if (rt == 256 || rt == 512 || rt == 1024) p->ring_threads = rt;
+            const int rb = env_int("DMWF_RING_BIG_THREADS", 1024), rs = env_int("DMWF_RING_SMALL_THREADS", 512);
+            if (rb == 256 || rb == 512 || rb == 1024) p->ring_big_threads = rb;
+            if (rs == 256 || rs == 512 || rs == 1024) p->ring_small_threads = rs;
+            const int sw = env_int("DMWF_SYN_WAVES", 4);
+            if (sw == 2 || sw == 4 || sw == 8) p->syn_waves = sw;
         }
         HIPCHK(hipStreamCreate(&p->stream));
         p->graphs = env_int("DMWF_GRAPHS", 1) != 0;
@@ -1604,6 +1609,24 @@ dm_status dm_refinement_trace(const dm_plan* p, double* history, int cap, int* n
     return DM_OK;
 }
 
+dm_status dm_transform_work(dm_plan* p, int64_t* points, int64_t* executed) {
+    return guarded(p, [&] {
+        REQUIRE(points && executed, DM_EINVAL, "null argument");
+        const size_t sn = (size_t)(p->mmax + 1) * p->npairs;
+        std::vector<int> ls(sn);
+        HIPCHK(hipMemcpyAsync(ls.data(), p->d_lstart, sn * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        int64_t ex = 0;
+        for (int m = 0; m <= p->mmax; ++m)
+            for (int q = 0; q < p->npairs; ++q) {
+                const int l0 = std::max(ls[(size_t)m * p->npairs + q], m);
+                if (l0 <= p->lmax) ex += p->lmax + 1 - l0;
+            }
+        *points = (int64_t)p->npairs * p->nalm;
+        *executed = ex;
+    });
+}
+
 dm_status dm_set_adaptive_resolution(dm_plan* p, double factor) {
     return guarded(p, [&] {
         REQUIRE(factor == 0.0 || (std::isfinite(factor) && factor >= 1.0), DM_EINVAL,
@@ -1901,33 +1924,50 @@ dm_status dm_iterate(dm_plan* p, int nrhs, const double* d, const double* t_in, 
     });
 }
 
-dm_status dm_autotune(dm_plan* p, int nrhs, int* chunks, double* ms) {
+// current choices [syn mchunk, ana mchunk, syn waves, ring big threads, ring small threads]
+static void tune_choice(const dm_plan* p, int* choice) {
+    if (!choice) return;
+    choice[0] = p->syn_mchunk;
+    choice[1] = p->ana_mchunk;
+    choice[2] = p->syn_waves;
+    choice[3] = p->ring_big_threads;
+    choice[4] = p->ring_small_threads;
+}
+
+dm_status dm_autotune(dm_plan* p, int nrhs, int* choice, double* ms) {
     return guarded(p, [&] {
         check_rhs(p, nrhs);
-        if (ms) ms[0] = ms[1] = 0.0;
-        if (!use_mfma(p, nrhs)) {
-            if (chunks) { chunks[0] = p->syn_mchunk; chunks[1] = p->ana_mchunk; }
+        if (ms) ms[0] = ms[1] = ms[2] = 0.0;
+        const bool batched = use_mfma(p, nrhs);
+        const bool classes = p->ring_classes && nrhs >= 4;
+        if (!batched && !classes) {
+            tune_choice(p, choice);
             return;
         }
-        // cache key: grid, lmax, precision, column tiles of 8 RHS
+        // cache key: grid, lmax, precision, column tiles of 8 RHS, ring classes in use
         char key[160];
-        std::snprintf(key, sizeof key, "g%d_%d_%d_%d_l%d_p%d_t%d", p->grid.kind, p->grid.nside, p->grid.ntheta,
-                      p->grid.nphi, p->lmax, (int)p->precision, (nrhs + 7) / 8);
+        std::snprintf(key, sizeof key, "g%d_%d_%d_%d_l%d_p%d_t%d_c%d", p->grid.kind, p->grid.nside, p->grid.ntheta,
+                      p->grid.nphi, p->lmax, (int)p->precision, (nrhs + 7) / 8, classes ? 1 : 0);
         const char* cache = std::getenv("DMWF_TUNE_CACHE");
         if (cache && cache[0]) {
             if (std::FILE* f = std::fopen(cache, "r")) {
                 char k[160];
-                int a = -1, b = -1;
+                int v[5];
                 bool hit = false;
-                while (std::fscanf(f, "%159s %d %d", k, &a, &b) == 3)
-                    if (std::strcmp(k, key) == 0 && a >= 0 && a <= 16 && b >= 0 && b <= 16) {
-                        p->syn_mchunk = a;
-                        p->ana_mchunk = b;
+                while (std::fscanf(f, "%159s %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 6)
+                    if (std::strcmp(k, key) == 0 && v[0] >= 0 && v[0] <= 16 && v[1] >= 0 && v[1] <= 16 &&
+                        (v[2] == 2 || v[2] == 4 || v[2] == 8) && (v[3] == 512 || v[3] == 1024) &&
+                        (v[4] == 256 || v[4] == 512 || v[4] == 1024)) {
+                        p->syn_mchunk = v[0];
+                        p->ana_mchunk = v[1];
+                        p->syn_waves = v[2];
+                        p->ring_big_threads = v[3];
+                        p->ring_small_threads = v[4];
                         hit = true;
                     }
                 std::fclose(f);
                 if (hit) {
-                    if (chunks) { chunks[0] = p->syn_mchunk; chunks[1] = p->ana_mchunk; }
+                    tune_choice(p, choice);
                     return;
                 }
             }
@@ -1956,27 +1996,60 @@ dm_status dm_autotune(dm_plan* p, int nrhs, int* chunks, double* ms) {
             }
             return (double)best;
         };
-        const int cand[] = {0, 1, 2, 4, 8};
-        double best_syn = 1e300, best_ana = 1e300;
-        int syn = p->syn_mchunk, ana = p->ana_mchunk;
-        p->mfma_nct = 1;
-        for (int c : cand) {
-            p->syn_mchunk = c;
-            const double t = timeit([&] { return launch_bsyn(p, nrhs, p->d_alm_spin, const_cast<void*>(phase), p->stream); });
-            if (t < best_syn) { best_syn = t; syn = c; }
+        double best_syn = 0.0, best_ana = 0.0, best_ring = 0.0;
+        if (batched) {
+            // synthesis: waves per block x m-chunk; analysis: m-chunk.  Both
+            // only move work between waves, blocks and XCDs: the arithmetic
+            // of every output stays the same, to the last bit
+            const int cand[] = {0, 1, 2, 4, 8};
+            const int waves[] = {2, 4, 8};
+            best_syn = best_ana = 1e300;
+            int syn = p->syn_mchunk, ana = p->ana_mchunk, sw = p->syn_waves;
+            p->mfma_nct = 1;
+            for (int w : waves)
+                for (int c : cand) {
+                    p->syn_waves = w;
+                    p->syn_mchunk = c;
+                    const double t =
+                        timeit([&] { return launch_bsyn(p, nrhs, p->d_alm_spin, const_cast<void*>(phase), p->stream); });
+                    if (t < best_syn) { best_syn = t; syn = c; sw = w; }
+                }
+            for (int c : cand) {
+                p->ana_mchunk = c;
+                const double t = timeit([&] { return launch_bana(p, nrhs, phase, p->d_pair_w, p->d_partial, p->stream); });
+                if (t < best_ana) { best_ana = t; ana = c; }
+            }
+            p->syn_mchunk = syn;
+            p->ana_mchunk = ana;
+            p->syn_waves = sw;
         }
-        for (int c : cand) {
-            p->ana_mchunk = c;
-            const double t = timeit([&] { return launch_bana(p, nrhs, phase, p->d_pair_w, p->d_partial, p->stream); });
-            if (t < best_ana) { best_ana = t; ana = c; }
+        if (classes) {
+            // the ring step's two launches: workgroup widths of the large and
+            // the small transforms (a width changes the order in which a few
+            // first-pixel rotations are accumulated: results move by FP64
+            // rounding only), timed on the pixel-update pass
+            const int bigc[] = {512, 1024}, smallc[] = {256, 512, 1024};
+            best_ring = 1e300;
+            int rb = p->ring_big_threads, rs = p->ring_small_threads;
+            for (int b : bigc)
+                for (int c : smallc) {
+                    p->ring_big_threads = b;
+                    p->ring_small_threads = c;
+                    const double t = timeit([&] {
+                        return launch_ring(p, RING_ITERATE, nrhs, nullptr, nullptr, p->d_K, p->d_b,
+                                           const_cast<void*>(phase), phase32(p, nrhs), p->stream);
+                    });
+                    if (t < best_ring) { best_ring = t; rb = b; rs = c; }
+                }
+            p->ring_big_threads = rb;
+            p->ring_small_threads = rs;
         }
-        p->syn_mchunk = syn;
-        p->ana_mchunk = ana;
-        if (chunks) { chunks[0] = syn; chunks[1] = ana; }
-        if (ms) { ms[0] = best_syn; ms[1] = best_ana; }
+        tune_choice(p, choice);
+        if (ms) { ms[0] = best_syn; ms[1] = best_ana; ms[2] = best_ring; }
         if (cache && cache[0])
             if (std::FILE* f = std::fopen(cache, "a")) {
-                std::fprintf(f, "%s %d %d\n", key, syn, ana);
+                std::fprintf(f, "%s %d %d %d %d %d\n", key, p->syn_mchunk, p->ana_mchunk, p->syn_waves,
+                             p->ring_big_threads, p->ring_small_threads);
                 std::fclose(f);
             }
     });

@@ -115,6 +115,9 @@ struct dm_plan {
     int syn_mchunk = 4, ana_mchunk = 4;               // batched kernels: consecutive m per XCD chunk
     int fft_threads = 512;          // threads of a split-ring workgroup
     int ring_threads = 512;         // threads of a whole-ring workgroup (<= 1024)
+    int ring_big_threads = 1024;    // the same for the two size classes' launches
+    int ring_small_threads = 512;
+    int syn_waves = 4;              // waves per block of the batched synthesis (2, 4 or 8)
     // ring pairs of the unsplit and the split lengths (the split launch runs
     // only when some length is split)
     int n_whole = 0, n_split = 0;

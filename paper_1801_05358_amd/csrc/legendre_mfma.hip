@@ -250,14 +250,14 @@ __device__ __forceinline__ void rec_next(const double* __restrict__ cf, int l, R
 }
 
 // ---------------------------------------------------------------------------
-// synthesis: 4 waves x PW ring pairs per block (PW = 64 FP32, 32 FP64),
+// synthesis: W waves x PW ring pairs per block (PW = 64 FP32, 32 FP64; W =
+// 2, 4 or 8, picked by the autotuner, 4 by default),
 // rounds of 4 degrees (one K step), one column tile of 8 RHS per block.
 // The rows of one matrix instruction are 16 ring pairs of one side: the
 // north rows take (lam, +2lam, -2lam) times D_f, the mirror rows
 // (lam, -2lam, +2lam) times eps_l D_f, with the sign on the B operand (per
 // lane, fixed for the kernel since rounds advance by 4 degrees).
 // ---------------------------------------------------------------------------
-constexpr int kSynWaves = 4;
 
 // [f = lam, +2, -2][degree in round][pair]; FP32 operand reads of one
 // instruction (16 pairs x 4 degrees, 32 lanes at a time) are conflict-free
@@ -303,7 +303,7 @@ __device__ __forceinline__ void bsyn_mfma(const SynTile<T, PW>& tl, int k, int r
     }
 }
 
-template <typename T, int PW>
+template <typename T, int PW, int kSynWaves>
 __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const double2* __restrict__ spin,
                                                               T* __restrict__ phase) {
     typedef typename Mfma<T>::v4 v4;
@@ -735,18 +735,25 @@ int batched_analysis_slots(dm_plan* p) {
     return (p->npairs + per - 1) / per;
 }
 
+template <int W>
+void launch_bsyn_w(dm_plan* p, BatchArgs A, int nrhs, const double2* sp, void* phase, hipStream_t s) {
+    const int pw = p->precision == DM_MIXED ? 64 : 32;
+    A.nx = (p->npairs + pw * W - 1) / (pw * W);
+    dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
+    dim3 block(64 * W);
+    if (p->precision == DM_MIXED)
+        hipLaunchKernelGGL((bsyn_kernel<float, 64, W>), grid, block, 0, s, A, sp, static_cast<float*>(phase));
+    else
+        hipLaunchKernelGGL((bsyn_kernel<double, 32, W>), grid, block, 0, s, A, sp, static_cast<double*>(phase));
+}
+
 hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, void* phase, hipStream_t s) {
     BatchArgs A = batch_args(p, nrhs);
-    const int pw = p->precision == DM_MIXED ? 64 : 32;
-    A.nx = (p->npairs + pw * kSynWaves - 1) / (pw * kSynWaves);
     A.mchunk = p->syn_mchunk;
-    dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
-    dim3 block(64 * kSynWaves);
     const double2* sp = reinterpret_cast<const double2*>(spin);
-    if (p->precision == DM_MIXED)
-        hipLaunchKernelGGL((bsyn_kernel<float, 64>), grid, block, 0, s, A, sp, static_cast<float*>(phase));
-    else
-        hipLaunchKernelGGL((bsyn_kernel<double, 32>), grid, block, 0, s, A, sp, static_cast<double*>(phase));
+    if (p->syn_waves == 2) launch_bsyn_w<2>(p, A, nrhs, sp, phase, s);
+    else if (p->syn_waves == 8) launch_bsyn_w<8>(p, A, nrhs, sp, phase, s);
+    else launch_bsyn_w<4>(p, A, nrhs, sp, phase, s);
     return hipGetLastError();
 }
 

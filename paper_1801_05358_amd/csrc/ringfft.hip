@@ -571,10 +571,13 @@ template <int MODE, typename R, typename P>
 void launch_both(dm_plan* p, const RingArgs<R>& A, const double* map_in, double* map_out, const double* K,
                  const double* b, C2<P>* ph, hipStream_t s) {
     if (p->ring_classes && A.nrhs >= kRingClassMinRhs) {
-        // the large transforms first, one 1024-thread workgroup per CU; then
-        // the others with a smaller buffer, two 512-thread workgroups per CU
-        launch_mode<MODE, 0, R, P>(A, p->n_big, p->d_plist_big, p->lds_big, 1024, map_in, map_out, K, b, ph, s);
-        launch_mode<MODE, 0, R, P>(A, p->n_small, p->d_plist_small, p->lds_small, 512, map_in, map_out, K, b, ph, s);
+        // the large transforms first, one workgroup per CU (1024 threads by
+        // default); then the others with a smaller buffer, two workgroups per
+        // CU (512 threads by default); the autotuner may pick other widths
+        launch_mode<MODE, 0, R, P>(A, p->n_big, p->d_plist_big, p->lds_big, p->ring_big_threads, map_in, map_out, K,
+                                   b, ph, s);
+        launch_mode<MODE, 0, R, P>(A, p->n_small, p->d_plist_small, p->lds_small, p->ring_small_threads, map_in,
+                                   map_out, K, b, ph, s);
     } else if (p->n_split == 0) {
         launch_mode<MODE, 0, R, P>(A, p->npairs, nullptr, p->fft.lds_elems, p->ring_threads, map_in, map_out, K, b,
                                    ph, s);

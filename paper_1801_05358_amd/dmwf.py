@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 # the DMWF_ABI_VERSION of include/dmwf.h these signatures follow
-ABI_VERSION = 9
+ABI_VERSION = 11
 
 DM_OK, DM_EINVAL, DM_ENOMEM, DM_EDEVICE, DM_ENONFINITE, DM_ESTATE, DM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "DM_OK", -1: "DM_EINVAL", -2: "DM_ENOMEM", -3: "DM_EDEVICE", -4: "DM_ENONFINITE",
@@ -135,6 +135,7 @@ def lib():
         "dm_checkpoint_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "dm_checkpoint_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "dm_iterate": (ctypes.c_int, [_P, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]),
+        "dm_transform_work": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "dm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
         "dm_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]),
         "dm_last_error": (ctypes.c_char_p, [_P]),
@@ -157,7 +158,7 @@ def exported_symbols():
             "dm_set_diagnostics", "dm_diagnostics_trace", "dm_set_adaptive_resolution", "dm_step_band_limits", "dm_wiener_filter",
             "dm_wiener_filter_device", "dm_wiener_filter_device_f32",
             "dm_constrained_realizations", "dm_alm2map", "dm_map2alm", "dm_alm2map_adjoint", "dm_alm2map_device",
-            "dm_map2alm_device", "dm_map2alm_device_noalloc", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
+            "dm_map2alm_device", "dm_map2alm_device_noalloc", "dm_autotune", "dm_checkpoint_save", "dm_checkpoint_load", "dm_iterate", "dm_transform_work", "dm_profile_enable", "dm_kernel_times", "dm_last_error"]
 
 
 def device_count():
@@ -279,12 +280,14 @@ class Plan:
         self._check(lib().dm_set_schedule(self._h, ctypes.byref(s)))
 
     def autotune(self, nrhs):
-        """Pick the batched Legendre kernels' m-chunks for nrhs RHS; returns
-        dict(syn_mchunk, ana_mchunk, syn_ms, ana_ms)."""
-        ch = (ctypes.c_int * 2)()
-        ms = (ctypes.c_double * 2)()
+        """Pick the launch shapes for nrhs RHS; returns dict(syn_mchunk,
+        ana_mchunk, syn_waves, ring_big_threads, ring_small_threads, syn_ms,
+        ana_ms, ring_ms)."""
+        ch = (ctypes.c_int * 5)()
+        ms = (ctypes.c_double * 3)()
         self._check(lib().dm_autotune(self._h, int(nrhs), ch, ms))
-        return dict(syn_mchunk=ch[0], ana_mchunk=ch[1], syn_ms=ms[0], ana_ms=ms[1])
+        return dict(syn_mchunk=ch[0], ana_mchunk=ch[1], syn_waves=ch[2], ring_big_threads=ch[3],
+                    ring_small_threads=ch[4], syn_ms=ms[0], ana_ms=ms[1], ring_ms=ms[2])
 
     def checkpoint_save(self, path):
         """Write where the last Wiener filter solve stopped to path."""
@@ -468,6 +471,13 @@ class Plan:
         if d.ndim == 2:
             return alm[0], tout[0]
         return alm, tout
+
+    def transform_work(self):
+        """(points, executed) of one Legendre transform per RHS: ring pairs x
+        nalm, and the points at or above their start degrees."""
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(lib().dm_transform_work(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     # -- profiling ---------------------------------------------------------
     def profile(self, enable=True):

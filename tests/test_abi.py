@@ -49,7 +49,7 @@ def test_binding_covers_header():
 
 def test_abi_version(lib):
     lib.dm_abi_version.restype = ctypes.c_int
-    assert lib.dm_abi_version() == 9
+    assert lib.dm_abi_version() == 11
     from paper_1801_05358_amd import dmwf
     header = open(HEADER).read()
     assert f"#define DMWF_ABI_VERSION {dmwf.ABI_VERSION}\n" in header

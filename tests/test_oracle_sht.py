@@ -159,3 +159,18 @@ def test_unchunked_equals_chunked():
     assert np.allclose(s1.synthesis(a), s2.synthesis(a), atol=1e-14)
     m = rng.standard_normal((3, g["npix"]))
     assert np.allclose(s1.adjoint(m), s2.adjoint(m), atol=1e-13)
+
+
+def test_adjoint_over_ring_subsets_sums_to_the_whole():
+    """The sampled adjoint (a partial sum over the given rings) over a
+    partition of the rings adds up to the full adjoint."""
+    lmax = 8
+    g = healpix_grid(4)
+    sht = SHT(g, lmax)
+    rng = np.random.default_rng(3)
+    maps = rng.standard_normal((3, g["npix"]))
+    nr = len(g["theta"])
+    parts = [np.arange(0, nr, 3), np.arange(1, nr, 3), np.arange(2, nr, 3)]
+    total = sum(sht.adjoint(maps, rings=r) for r in parts)
+    full = sht.adjoint(maps)
+    assert np.abs(total - full).max() <= 1e-13 * np.abs(full).max()
