@@ -175,6 +175,11 @@ def counter_summary(csv_paths, out, command, title, last):
                 continue
             d = vals.setdefault(k, {}).setdefault(r["Counter_Name"], {})
             d[int(r["Dispatch_Id"])] = d.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+            # the dispatch's duration (ns) from its timestamps, once per dispatch and pass
+            t = vals[k].setdefault("duration_ns", {})
+            key = (path, int(r["Dispatch_Id"]))
+            if key not in t:
+                t[key] = float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     lines = [f"# {title}", f"# command (one run per pass): {command}",
              f"# per kernel: counter averages over its last {last} dispatches"]
     for k in sorted(vals):
@@ -189,9 +194,10 @@ def counter_summary(csv_paths, out, command, title, last):
         if "SQ_INSTS_VALU_MFMA_MOPS_F32" in avg or "SQ_INSTS_VALU_MFMA_MOPS_F64" in avg:
             fl = 512.0 * (avg.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) + avg.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0))
             lines.append(f"derived_mfma_flop: {fl:.6e}")
-        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and avg.get("GRBM_GUI_ACTIVE"):
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and avg.get("duration_ns"):
+            # busy cycles summed over the 1024 SIMDs, over the dispatch's cycles at the peak clock
             lines.append(f"derived_mfma_busy_frac: "
-                         f"{avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (avg['GRBM_GUI_ACTIVE'] * 1024):.4f}")
+                         f"{avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (1024 * avg['duration_ns'] * CLOCK_GHZ):.4f}")
         mf = avg.get("SQ_INSTS_MFMA") or (avg.get("SQ_INSTS_VALU_MFMA_F32", 0.0) + avg.get("SQ_INSTS_VALU_MFMA_F64", 0.0))
         if mf:
             if "SQ_INSTS_VALU" in avg:
@@ -393,6 +399,8 @@ def main():
                     help="diag: diagonal noise, one mask; corr: correlated 3x3 noise with distinct T and P masks")
     ap.add_argument("--refine", type=int, default=0,
                     help="also run one solve with this many Appendix A corrections and report its residuals")
+    ap.add_argument("--adaptive", type=float, default=0.0,
+                    help="adaptive working resolution factor (>= 1; 0 = off) for the timed and reference solves")
     ap.add_argument("--eps-table", action="store_true",
                     help="instead of the headline: Algorithm 1 under its stopping rule (Sec. 3.2 settings) for "
                          "final thresholds 1e-4, 1e-5, 1e-6 on one RHS (FP64), iterations, time, chi2 and residual "
@@ -453,6 +461,8 @@ def main():
         plan = dmwf.Plan(lmax=lmax, nside=nside, max_rhs=nrhs, device=0, precision=prec)
         plan.set_spectra(prob["cl"])
         plan.set_noise(ncov, obs)
+        if args.adaptive:
+            plan.set_adaptive_resolution(args.adaptive)
         return plan
 
     def set_iters(plan, k):
@@ -503,7 +513,11 @@ def main():
     log(f"[bench] timed {args.steps} iterations in {dt:.3f} s")
     # per-kernel times (HIP events on the launch stream) from a separate run,
     # so that the events do not perturb the timed one
-    prof_it = min(args.steps, 20)
+    # the band limits of the timed schedule (adaptive working resolution)
+    band = plan.step_band_limits().tolist()
+    # (with adaptive resolution the profiled run repeats the timed schedule,
+    # so that its kernel times average over the same band limits)
+    prof_it = args.steps if args.adaptive else min(args.steps, 20)
     set_iters(plan, prof_it)
     prof_t = torch.empty_like(out_t)
     plan.profile(True)
@@ -519,6 +533,9 @@ def main():
     dom = max(("legendre_analysis", "legendre_synthesis"), key=lambda k: kt[k][0])
     ms, n = kt[dom]
     flops = legendre_flops(plan.nrings // 2 + 1, plan.nalm, B)
+    if args.adaptive and band:
+        # per launch, averaged over the schedule: the points up to each step's band limit
+        flops = sum(legendre_flops(plan.nrings // 2 + 1, (L + 1) * (L + 2) // 2, B) for L in band) / len(band)
     achieved = flops / (ms / n * 1e-3) / 1e12
     batched = B >= 8 or args.precision == "mixed"
     if args.precision == "mixed":
@@ -552,7 +569,8 @@ def main():
                                f"mask |b|<{band:.4g} deg + {holes} holes of 0.5 deg, scan noise {dyn:g}:1 "
                                f"(Q = U = 2 T), ") +
                                f"cooling lambda 1e3 -> 1 in steps of 10 "
-                               f"iterations, {B} right-hand sides per launch ({prec_text})",
+                               f"iterations, {B} right-hand sides per launch ({prec_text})" +
+                               (f", adaptive working resolution factor {args.adaptive:g}" if args.adaptive else ""),
                    "recipe": f"configuration {cfg}", "nside": nside, "lmax": lmax, "nrhs": B,
                    "precision": args.precision, "noise": args.noise},
         "setup_s": round(setup_s, 3),
@@ -572,6 +590,11 @@ def main():
                          "unit": "GB/s", "frac": round(rb / (ring_ms / max(ring_n, 1) * 1e-3) / 1e9 / HBM_PEAK, 4),
                          "algorithmic_bytes": rb, "traffic": ring_traffic},
     }
+
+    if args.adaptive:
+        rec["adaptive_resolution"] = {"factor": args.adaptive,
+                                      "band_limits_per_cooling_step": band,
+                                      "note": "roofline flops averaged over the cooling steps' band limits"}
 
     if args.refine > 0:
         # Appendix A's corrections on the same batch and schedule (reported

@@ -151,7 +151,7 @@ int dm_device_count(void);
  * result beyond FP rounding except DMWF_RING_FP32:
  *   DMWF_MFMA=0|1          batched matrix-core Legendre kernels off / on
  *   DMWF_SYN_MCHUNK, DMWF_ANA_MCHUNK   their m-chunk per XCD (see dm_autotune)
- *   DMWF_SYN_WAVES=2|4|8   waves per block of the batched synthesis
+ *   DMWF_SYN_WAVES=1|2|4|8 waves per block of the batched synthesis
  *   DMWF_RING_BIG_THREADS, DMWF_RING_SMALL_THREADS   ring size-class widths
  *   DMWF_SYN_THREADS, DMWF_SYN_R, DMWF_ANA_R   single-RHS kernel tiling
  *   DMWF_GRAPHS=0          fixed-schedule steps launched directly, not as graphs
@@ -412,7 +412,7 @@ dm_status dm_checkpoint_load(dm_plan* plan, const char* path);
 /* Autotuner of the launch shapes of a solve with nrhs right-hand sides,
  * timed on the plan's own buffers, keeping the fastest for this plan:
  *  - batched matrix-core Legendre kernels (from 2 RHS on for DM_MIXED, 8
- *    for DM_FP64): the synthesis' waves per block (2, 4, 8) together with
+ *    for DM_FP64): the synthesis' waves per block (1, 2, 4, 8) together with
  *    its m-chunk, and the analysis' m-chunk (how many consecutive m a chunk
  *    of workgroups on one XCD covers: 0, 1, 2, 4, 8).  These only move work
  *    between waves, workgroups and XCDs: results stay the same to the last

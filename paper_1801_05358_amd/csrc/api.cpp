@@ -1035,7 +1035,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
             if (rb == 256 || rb == 512 || rb == 1024) p->ring_big_threads = rb;
             if (rs == 256 || rs == 512 || rs == 1024) p->ring_small_threads = rs;
             const int sw = env_int("DMWF_SYN_WAVES", 4);
-            if (sw == 2 || sw == 4 || sw == 8) p->syn_waves = sw;
+            if (sw == 1 || sw == 2 || sw == 4 || sw == 8) p->syn_waves = sw;
         }
         HIPCHK(hipStreamCreate(&p->stream));
         p->graphs = env_int("DMWF_GRAPHS", 1) != 0;
@@ -1956,7 +1956,7 @@ dm_status dm_autotune(dm_plan* p, int nrhs, int* choice, double* ms) {
                 bool hit = false;
                 while (std::fscanf(f, "%159s %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 6)
                     if (std::strcmp(k, key) == 0 && v[0] >= 0 && v[0] <= 16 && v[1] >= 0 && v[1] <= 16 &&
-                        (v[2] == 2 || v[2] == 4 || v[2] == 8) && (v[3] == 512 || v[3] == 1024) &&
+                        (v[2] == 1 || v[2] == 2 || v[2] == 4 || v[2] == 8) && (v[3] == 512 || v[3] == 1024) &&
                         (v[4] == 256 || v[4] == 512 || v[4] == 1024)) {
                         p->syn_mchunk = v[0];
                         p->ana_mchunk = v[1];
@@ -2002,7 +2002,7 @@ dm_status dm_autotune(dm_plan* p, int nrhs, int* choice, double* ms) {
             // only move work between waves, blocks and XCDs: the arithmetic
             // of every output stays the same, to the last bit
             const int cand[] = {0, 1, 2, 4, 8};
-            const int waves[] = {2, 4, 8};
+            const int waves[] = {1, 2, 4, 8};
             best_syn = best_ana = 1e300;
             int syn = p->syn_mchunk, ana = p->ana_mchunk, sw = p->syn_waves;
             p->mfma_nct = 1;

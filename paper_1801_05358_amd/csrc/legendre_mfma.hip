@@ -251,7 +251,7 @@ __device__ __forceinline__ void rec_next(const double* __restrict__ cf, int l, R
 
 // ---------------------------------------------------------------------------
 // synthesis: W waves x PW ring pairs per block (PW = 64 FP32, 32 FP64; W =
-// 2, 4 or 8, picked by the autotuner, 4 by default),
+// 1, 2, 4 or 8, picked by the autotuner, 4 by default),
 // rounds of 4 degrees (one K step), one column tile of 8 RHS per block.
 // The rows of one matrix instruction are 16 ring pairs of one side: the
 // north rows take (lam, +2lam, -2lam) times D_f, the mirror rows
@@ -751,7 +751,8 @@ hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, void* phase, hi
     BatchArgs A = batch_args(p, nrhs);
     A.mchunk = p->syn_mchunk;
     const double2* sp = reinterpret_cast<const double2*>(spin);
-    if (p->syn_waves == 2) launch_bsyn_w<2>(p, A, nrhs, sp, phase, s);
+    if (p->syn_waves == 1) launch_bsyn_w<1>(p, A, nrhs, sp, phase, s);
+    else if (p->syn_waves == 2) launch_bsyn_w<2>(p, A, nrhs, sp, phase, s);
     else if (p->syn_waves == 8) launch_bsyn_w<8>(p, A, nrhs, sp, phase, s);
     else launch_bsyn_w<4>(p, A, nrhs, sp, phase, s);
     return hipGetLastError();

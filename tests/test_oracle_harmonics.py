@@ -104,3 +104,44 @@ def test_north_south_parity():
         ell = np.arange(lmax + 1)
         sign = (-1.0) ** (ell[:, None] + ms[None, :])
         assert np.allclose(a, sign[None] * b, atol=1e-13)
+
+
+def test_polar_recurrence_floor():
+    """The rounding floor of a three-term recurrence near the poles, which
+    the full-size GPU tests allow on polar rings (lmax^2 * 8.8e-16 of the
+    ring's largest value): the oracle's FP64 spin-0 functions on the first
+    HEALPix ring at Nside 1024 up to l = 2048, against the same recurrence
+    run in the x87 80-bit format from its closed-form seed, deviate by at
+    most lmax^2 * 8.8e-16 of each order's largest value; measured: 3.7e-11
+    (the check below that it exceeds 1e-13 keeps the measurement honest)."""
+    if np.finfo(np.longdouble).nmant < 60:
+        pytest.skip("no extended precision long double on this host")
+    from oracle.geometry import healpix_grid
+    nside, lmax = 1024, 2048
+    th = healpix_grid(nside)["theta"][0]
+    # on this ring (sin theta = 8e-4) only the lowest orders reach their
+    # oscillating regime (l sin theta > m) below l = 2048
+    ms = np.array([0, 1, 2, 3, 5])
+    lam = spin_lambda(lmax, 0, np.array([th]), ms)[0]          # [l, m]
+    L = np.longdouble
+    x, sx = np.cos(L(th)), np.sin(L(th))
+    worst = 0.0
+    for k, m in enumerate(ms):
+        # seed lam_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{j<=m} (2j-1)/(2j)) sin^m
+        v = L(1) / (L(4) * L(np.pi))
+        for j in range(1, m + 1):
+            v *= L(2 * j - 1) / L(2 * j)
+        v = np.sqrt(v * L(2 * m + 1)) * (L(-1) ** m) * sx ** m
+        prev, cur = L(0), v
+        ref = np.zeros(lmax + 1, dtype=np.longdouble)
+        ref[m] = cur
+        for l in range(m + 1, lmax + 1):
+            a = np.sqrt((L(4) * l * l - 1) / (L(l) * l - L(m) * m))
+            b = np.sqrt((L(2) * l + 1) * (L(l - 1) ** 2 - L(m) ** 2) / ((L(2) * l - 3) * (L(l) ** 2 - L(m) ** 2)))
+            prev, cur = cur, a * x * cur - b * prev
+            ref[l] = cur
+        scale = float(np.max(np.abs(ref)))
+        dev = float(np.max(np.abs(lam[:, k] - ref.astype(np.float64)))) / scale
+        worst = max(worst, dev)
+        assert dev <= lmax ** 2 * 8.8e-16, (m, dev)
+    assert worst > 1e-13, worst
