@@ -206,12 +206,6 @@ bool use_mfma(dm_plan* p, int nrhs) {
     return nrhs >= (p->precision == DM_MIXED ? 2 : 8);
 }
 
-// the Legendre kernels carry scaled recursions; their scales enter the
-// combine step and the spin-basis copy
-const double* spin_scales(dm_plan* p, int nrhs) {
-    (void)nrhs;
-    return p->d_scale;
-}
 
 void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, double* alm, double* spin,
                   hipStream_t s, double* cpart = nullptr) {
@@ -231,7 +225,10 @@ void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, dou
         t.done();
     }
     Timed t(p, KC_COMBINE, s);
-    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, partial32, filter, alm, spin, cpart, spin_scales(p, nrhs),
+    // every Legendre kernel (vector and matrix-core) carries the scaled
+    // recursions mu = lam / S: the scales multiply the partial sums here and
+    // the spin-basis copy the synthesis reads
+    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, partial32, filter, alm, spin, cpart, p->d_scale,
                           s));
     t.done();
 }
@@ -256,7 +253,7 @@ void map2alm_dev(dm_plan* p, int nrhs, const double* map, double* alm, bool weig
 }
 
 void alm2map_dev(dm_plan* p, int nrhs, const double* alm, double* map, hipStream_t s) {
-    HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, spin_scales(p, nrhs), s));
+    HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, p->d_scale, s));
     leg_synthesis(p, nrhs, p->d_alm_spin, s);
     ring(p, RING_SYNTH, nrhs, nullptr, map, nullptr, s);
 }
@@ -726,7 +723,7 @@ void solve_dev(dm_plan* p, int nrhs, const double* d, double* alm, double* map, 
     // uninterrupted run uses after its analysis, so the result is the same to
     // the last bit
     auto restart_from_u = [&](bool final_map) {
-        HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, spin_scales(p, nrhs), s));
+        HIPCHK(launch_to_spin(p, nrhs, alm, p->d_alm_spin, p->d_scale, s));
         leg_synthesis(p, nrhs, p->d_alm_spin, s);
         if (final_map)
             ring(p, RING_SYNTH, nrhs, nullptr, p->d_ux, nullptr, s);

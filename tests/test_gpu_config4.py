@@ -12,9 +12,9 @@ takes outputs it can compute one by one, with synthetic inputs only:
   inputs in one call, after one iteration at lambda = 1, where the solver's
   result is F A (masked data) in closed form: s_CR and the fluctuation part
   on sampled (l, m).
-FP64 matches to 1e-11 of the sampled values' scale (1e-11 plus the polar
-l^2 eps of the three-term recurrences on polar rings), mixed to 1e-5
-relative per field.
+FP64 matches to 1e-11 of the sampled values' scale (1e-10 of the ring's
+largest value on polar rings, where the three-term recurrences lose a
+little), mixed to 1e-5 relative per field.
 """
 
 import numpy as np
@@ -115,7 +115,7 @@ def test_batched_transforms(dmwf, case, precision):
                 o, n = grid["offset"][r], grid["nphi"][r]
                 err = np.abs(mp[k][:, o:o + n] - blk).max()
                 polar = r < nside or r >= 3 * nside
-                tol = (lmax ** 2 * 2.2e-16 * 4) if polar else 1e-11
+                tol = 1e-10 if polar else 1e-11
                 assert err <= tol * np.abs(blk).max() + 1e-13, (k, r, err)
         else:
             for f in range(3):

@@ -285,10 +285,11 @@ def test_full_size_sampled_transforms(nside, lmax, dmwf):
         # one and the library's normalised one) lose accuracy as l grows:
         # the oracle's functions on the first ring at Nside 1024 deviate by
         # 3.7e-11 of each order's largest value from an 80-bit recurrence
-        # (tests/test_oracle_harmonics.py), inside the l^2 eps allowance
-        # used here.  Elsewhere FP64 rounding is far below 1e-11.
+        # (tests/test_oracle_harmonics.py); the library and the oracle agree
+        # to about 2e-11 of the ring's largest value there, within 1e-10.
+        # Elsewhere FP64 rounding is far below 1e-11.
         polar = r < nside or r >= 3 * nside
-        tol = (lmax ** 2 * 2.2e-16 * 4) if polar else 1e-11
+        tol = 1e-10 if polar else 1e-11
         print(f"ring {r} {'polar' if polar else 'belt'} relative error {err / np.abs(blk).max():.3e}", flush=True)
         assert err <= tol * np.abs(blk).max() + 1e-13, (r, err)
     m = rng.standard_normal((3, grid["npix"]))
@@ -322,7 +323,7 @@ def test_full_size_two_launch_ring_step(dmwf):
             o, n = grid["offset"][r], grid["nphi"][r]
             err = np.abs(mp[k][:, o:o + n] - blk).max()
             polar = r < nside or r >= 3 * nside
-            tol = (lmax ** 2 * 2.2e-16 * 4) if polar else 1e-11
+            tol = 1e-10 if polar else 1e-11
             assert err <= tol * np.abs(blk).max() + 1e-13, (k, r, err)
     m = rng.standard_normal((nrhs, 3, grid["npix"]))
     alm = plan.map2alm(m)
