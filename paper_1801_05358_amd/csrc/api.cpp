@@ -908,6 +908,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_pair_x); dfree(p->d_pair_w); dfree(p->d_pair_one); dfree(p->d_pairs); dfree(p->d_fftlen);
     dfree(p->d_plist_whole); dfree(p->d_plist_split); dfree(p->d_plist_small); dfree(p->d_plist_big);
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
+    dfree(p->d_tw3); dfree(p->d_tw332);
     dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_coef_s); dfree(p->d_scale); dfree(p->d_lstart); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
     dfree(p->d_ninv6); dfree(p->d_tn6); dfree(p->d_state_u);
@@ -1015,7 +1016,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
             if (i4 > 2 * p->fft_threads) p->split_k = 4;
         }
         const int lds_max = std::max(p->fft.lds_elems, p->fft.lds_split);
-        p->fft_lds_bytes = (size_t)(lds_max + lds_max / 8 + 8) * 16;   // padded layout (ringfft.hip)
+        p->fft_lds_bytes = (size_t)(lds_max + lds_max / 8 + 32) * 16;  // padded layout (ringfft.hip)
         REQUIRE(p->fft_lds_bytes <= 160 * 1024, DM_EUNSUPPORTED,
                 "ring length needs a transform buffer of " + std::to_string(lds_max) +
                     " points, beyond the LDS of one workgroup in double precision");
@@ -1063,6 +1064,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
             fl[i].logM = p->fft.logM[i];
             fl[i].bluestein = p->fft.chirp_off[i] >= 0;
             fl[i].split = p->fft.split[i];
+            fl[i].r3 = p->fft.r3[i];
             fl[i].chirp_off = std::max<int64_t>(p->fft.chirp_off[i], 0);
             fl[i].bhat_off = std::max<int64_t>(p->fft.bhat_off[i], 0);
         }
@@ -1080,7 +1082,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
             }
             // size classes of the unsplit pairs (DMWF_RING_CLASSES=0 turns them off)
             std::vector<int> small, big;
-            // (4096 + 512 + 8) x 16 B = 72 KB; DMWF_RING_SMALL_M lowers the
+            // (4096 + 512 + 32) x 16 B = 72.5 KB; DMWF_RING_SMALL_M lowers the
             // bound, to exercise the two launches on small grids
             const int kSmallM = std::max(4, std::min(4096, env_int("DMWF_RING_SMALL_M", 4096)));
             for (int q : whole) (p->fft.M[pd[q].len_idx] <= kSmallM ? small : big).push_back(q);
@@ -1105,6 +1107,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         dalloc(p, p->d_chirp, p->fft.chirp.size());
         dalloc(p, p->d_bhat, p->fft.bhat.size());
         dalloc(p, p->d_tw, p->fft.tw.size());
+        dalloc(p, p->d_tw3, p->fft.tw3.size());
         upload(p, p->d_pair_x, px.data(), px.size());
         upload(p, p->d_pair_w, pw.data(), pw.size());
         upload(p, p->d_pair_one, one.data(), one.size());
@@ -1113,6 +1116,7 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         if (!p->fft.chirp.empty()) upload(p, p->d_chirp, p->fft.chirp.data(), p->fft.chirp.size());
         if (!p->fft.bhat.empty()) upload(p, p->d_bhat, p->fft.bhat.data(), p->fft.bhat.size());
         upload(p, p->d_tw, p->fft.tw.data(), p->fft.tw.size());
+        upload(p, p->d_tw3, p->fft.tw3.data(), p->fft.tw3.size());
         // FP32 ring transforms for a mixed plan: opt-in (DMWF_RING_FP32=1).
         // At Nside 1024, lmax 2048 they take the B-mode error of the mixed
         // solve from 4e-6 to 1.2e-5 relative, past the 1e-5 bar, so the
@@ -1120,13 +1124,16 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         const char* rf = std::getenv("DMWF_RING_FP32");
         if (precision == DM_MIXED && rf && std::atoi(rf) == 1) {
             auto to32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
-            const std::vector<float> c32 = to32(p->fft.chirp), b32 = to32(p->fft.bhat), t32 = to32(p->fft.tw);
+            const std::vector<float> c32 = to32(p->fft.chirp), b32 = to32(p->fft.bhat), t32 = to32(p->fft.tw),
+                                     t332 = to32(p->fft.tw3);
             dalloc(p, p->d_chirp32, c32.size());
             dalloc(p, p->d_bhat32, b32.size());
             dalloc(p, p->d_tw32, t32.size());
+            dalloc(p, p->d_tw332, t332.size());
             if (!c32.empty()) upload(p, p->d_chirp32, c32.data(), c32.size());
             if (!b32.empty()) upload(p, p->d_bhat32, b32.data(), b32.size());
             upload(p, p->d_tw32, t32.data(), t32.size());
+            upload(p, p->d_tw332, t332.data(), t332.size());
             HIPCHK(hipStreamSynchronize(p->stream));           // the host copies go out of scope
         }
         HIPCHK(ring_set_lds_limit(p->fft_lds_bytes));

@@ -39,9 +39,11 @@ struct FftTables {
     // distinct ring lengths
     std::vector<int> n;           // length
     std::vector<int> split;       // 1: n = 4 i transformed as four length-i DFTs
-    std::vector<int> M;           // transform size (n if n is a power of two, else the Bluestein
-                                  // size of n, or of n/4 when split)
-    std::vector<int> logM;
+    std::vector<int> M;           // transform size: n for n = 2^k or 3 2^k (direct), else the
+                                  // Bluestein size of n (or of n/4 when split): the smaller of
+                                  // 2^a and 3 2^b that is >= 2n - 1
+    std::vector<int> logM;        // log2 of M's power-of-two factor
+    std::vector<int> r3;          // 1: M = 3 2^logM (a radix-3 pass and three 2^logM blocks)
     std::vector<int64_t> chirp_off;   // offset into chirp (complex) or -1
     std::vector<int64_t> bhat_off;    // offset into bhat (complex) or -1
     int Mmax = 1;                 // largest power-of-two transform (the twiddle table's size)
@@ -50,6 +52,8 @@ struct FftTables {
     std::vector<double> chirp;    // interleaved complex, exp(-i pi j^2 / n)
     std::vector<double> bhat;     // interleaved complex, FFT_M(b) / M
     std::vector<double> tw;       // interleaved complex, exp(-2 pi i k / Mmax), k < Mmax/2
+    int P3max = 1;                // largest power-of-two factor P of a radix-3 size 3P
+    std::vector<double> tw3;      // interleaved complex, exp(-2 pi i e / (3 P3max)), e < 3 P3max
 };
 
 // Device view of everything the ring (FFT) kernel needs per pair.
@@ -62,7 +66,7 @@ struct RingPairDev {
 };
 
 struct FftLenDev {
-    int n, M, logM, bluestein, split;
+    int n, M, logM, bluestein, split, r3;
     int64_t chirp_off, bhat_off;
 };
 
@@ -96,9 +100,11 @@ struct dm_plan {
     double* d_chirp = nullptr;
     double* d_bhat = nullptr;
     double* d_tw = nullptr;
-    float* d_chirp32 = nullptr;        // FP32 copies of the three tables (mixed plans)
+    double* d_tw3 = nullptr;           // radix-3 twiddles
+    float* d_chirp32 = nullptr;        // FP32 copies of the four tables (mixed plans)
     float* d_bhat32 = nullptr;
     float* d_tw32 = nullptr;
+    float* d_tw332 = nullptr;
     double* d_coef = nullptr;          // [nalm][kCoefStride]
     double* d_coef_s = nullptr;        // [nalm][kCoefSStride] scaled recursions (batched kernels)
     double* d_scale = nullptr;         // [nalm][2] their scales S (spin 0, spin 2)

@@ -11,9 +11,10 @@
 //   update      t = K x + b  (eq 9 as t = u + T N^-1 (d - u));
 //   analysis    G_m = e^{-i m phi0} DFT(t)[m mod n], m = 0..mmax, split
 //               back into the two rings by Hermitian symmetry.
-// Lengths that are powers of two use a radix-2 FFT in LDS; other lengths
-// (most HEALPix polar rings, 4i) use Bluestein's chirp-z convolution with a
-// power-of-two FFT of size M >= 2n - 1, also in LDS.  Where that M would be
+// Lengths 2^k use a radix-2 FFT in LDS and lengths 3 2^k a radix-3 pass
+// joined to three radix-2 blocks (mixed radix); other lengths (most HEALPix
+// polar rings, 4i) use Bluestein's chirp-z convolution with an FFT of size
+// M >= 2n - 1, the smaller of 2^a and 3 2^b, also in LDS.  Where that M would be
 // the largest buffer of the plan, a length n = 4i is split by decimation
 // (four length-i Bluestein transforms and a radix-4 step), which needs
 // max(n, M_i) elements instead.  Inverse transforms are conj(DFT(conj(.))).
@@ -58,6 +59,8 @@ struct RingArgs {
     const C2<R>* __restrict__ chirp;
     const C2<R>* __restrict__ bhat;
     const C2<R>* __restrict__ tw;
+    const C2<R>* __restrict__ tw3;   // exp(-2 pi i e / (3 P3max)), e < 3 P3max
+    int P3max;
 };
 
 // LDS layout of a transform buffer of size M = 2^logM: element i at
@@ -83,6 +86,19 @@ __device__ __forceinline__ C conjc(C a) {
 }
 __device__ __forceinline__ unsigned brev(unsigned j, int logM) {
     return logM == 0 ? 0u : (__brev(j) >> (32 - logM));
+}
+
+// Slot of logical index j in a transform buffer of size M: bit reversal for
+// M = 2^logM; for M = 3 P (P = 2^logM) the mixed-radix digit reversal
+// (j mod 3) P + brev(j div 3), which is both the input order of the
+// decimation-in-time transform and the output order of the
+// decimation-in-frequency one below.
+__device__ __forceinline__ int perm(int j, const FftLenDev& L) {
+    if (L.r3) {
+        const int q = j / 3;
+        return (j - 3 * q) * (L.M / 3) + (int)brev((unsigned)q, L.logM);
+    }
+    return (int)brev((unsigned)j, L.logM);
 }
 
 // e^{i m phi0} with phi0 = pi / den (den = 0: phi0 = 0), reduced exactly
@@ -179,30 +195,73 @@ __device__ void fft_dif(C2<R>* buf, int M, int logM, int logMmax, const C2<R>* _
     else if (top == 1) fft_pass<R, 1, false>(buf, M, sh, 0, logMmax, tw, inv);
 }
 
-// Forward DFT core.  On entry buf[brev(j)] holds a_j (times chirp_j for
-// Bluestein, zeros at brev(j) for j >= n).  On exit the transform value X_k
-// is at buf[out_pos(k)] (times chirp_k for Bluestein).
+// The radix-3 pass of a size M = 3 P: elements k, P + k, 2P + k for
+// k < P.  Decimation in time (after three DIT transforms of length P, which
+// leave Y_r[k] at r P + k):  X[k + P q] = sum_r W_3^{r q} W_M^{r k} Y_r[k],
+// stored at q P + k, natural order.  Decimation in frequency (before three
+// DIF transforms of length P):  y_q[k] = W_M^{q k} sum_r W_3^{r q} x[k + P r],
+// stored at q P + k.  Twiddles W_M^e = tw3[e P3max / P]; inv conjugates every
+// root (the inverse transform).
+template <typename R, bool DIT>
+__device__ void r3_pass(C2<R>* buf, int P, int sh, const C2<R>* __restrict__ tw3, int P3max, bool inv) {
+    const int st = P3max / P;
+    const R h = R(0.86602540378443864676);          // sin(2 pi / 3)
+    const R sg = inv ? R(-1) : R(1);
+    for (int k = threadIdx.x; k < P; k += blockDim.x) {
+        C2<R> w1 = tw3[k * st], w2 = tw3[2 * k * st];
+        if (inv) { w1.y = -w1.y; w2.y = -w2.y; }
+        C2<R> x0 = buf[pidx(k, sh)], x1 = buf[pidx(P + k, sh)], x2 = buf[pidx(2 * P + k, sh)];
+        if (DIT) { x1 = cmul(x1, w1); x2 = cmul(x2, w2); }
+        const C2<R> t1 = mk<R>(x1.x + x2.x, x1.y + x2.y), t2 = mk<R>(x1.x - x2.x, x1.y - x2.y);
+        const C2<R> mid = mk<R>(x0.x - R(0.5) * t1.x, x0.y - R(0.5) * t1.y);
+        // -+ i sin(2 pi / 3) t2
+        const C2<R> it = mk<R>(sg * h * t2.y, -sg * h * t2.x);
+        C2<R> y1 = mk<R>(mid.x + it.x, mid.y + it.y), y2 = mk<R>(mid.x - it.x, mid.y - it.y);
+        if (!DIT) { y1 = cmul(y1, w1); y2 = cmul(y2, w2); }
+        buf[pidx(k, sh)] = mk<R>(x0.x + t1.x, x0.y + t1.y);
+        buf[pidx(P + k, sh)] = y1;
+        buf[pidx(2 * P + k, sh)] = y2;
+    }
+    __syncthreads();
+}
+
+// transforms of a buffer of size M (2^logM, or 3 2^logM as three aligned
+// blocks of 2^logM: the radix-2 passes never cross a block)
+template <typename R>
+__device__ void fft_dit_any(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A, bool inv) {
+    fft_dit<R>(buf, L.M, L.logM, A.logMmax, A.tw, inv);
+    if (L.r3) r3_pass<R, true>(buf, L.M / 3, pad_shift(L.logM), A.tw3, A.P3max, inv);
+}
+template <typename R>
+__device__ void fft_dif_any(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A, bool inv) {
+    if (L.r3) r3_pass<R, false>(buf, L.M / 3, pad_shift(L.logM), A.tw3, A.P3max, inv);
+    fft_dif<R>(buf, L.M, L.logM, A.logMmax, A.tw, inv);
+}
+
+// Forward DFT core.  On entry buf[perm(j)] holds a_j (times chirp_j for
+// Bluestein, zeros at perm(j) for j >= n).  On exit the transform value X_k
+// is at buf[k] (direct lengths) or buf[perm(k)] times chirp_k (Bluestein).
 template <typename R>
 __device__ void dft_core(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A) {
     if (!L.bluestein) {
-        fft_dit<R>(buf, L.M, L.logM, A.logMmax, A.tw, false);
+        fft_dit_any<R>(buf, L, A, false);
     } else {
-        fft_dit<R>(buf, L.M, L.logM, A.logMmax, A.tw, false);
+        fft_dit_any<R>(buf, L, A, false);
         const C2<R>* bh = A.bhat + L.bhat_off;
         const int sh = pad_shift(L.logM);
         for (int q = threadIdx.x; q < L.M; q += blockDim.x) buf[pidx(q, sh)] = cmul(buf[pidx(q, sh)], bh[q]);
         __syncthreads();
-        fft_dif<R>(buf, L.M, L.logM, A.logMmax, A.tw, true);
+        fft_dif_any<R>(buf, L, A, true);
     }
 }
 
 // Inverse-direction core for the synthesis: on entry buf holds conj(c)
-// placed for the transform; on exit x_j = conj(value at brev(j)) (times
-// chirp for Bluestein).  For powers of two the input is in natural order.
+// placed for the transform; on exit x_j = conj(value at perm(j)) (times
+// chirp for Bluestein).  For direct lengths the input is in natural order.
 template <typename R>
 __device__ void idft_core(C2<R>* buf, const FftLenDev& L, const RingArgs<R>& A) {
     if (!L.bluestein) {
-        fft_dif<R>(buf, L.M, L.logM, A.logMmax, A.tw, false);
+        fft_dif_any<R>(buf, L, A, false);
     } else {
         dft_core<R>(buf, L, A);
     }
@@ -416,7 +475,7 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
         if (synth) {
             // fold into n bins, place conj(C_N + i C_S) for the inverse
             // transform.  Lanes take consecutive logical indices j (coalesced
-            // ring-data reads; the slot is brev(j) for Bluestein lengths).
+            // ring-data reads; the slot is perm(j) for Bluestein lengths).
             // e^{i mstart phi0} = e^{i j phi0} e^{-i w n phi0} with
             // mstart = j - w n: the first factor advances by e^{i nt phi0}
             // from one j of a lane to the next, and the second is (-1)^w on
@@ -427,7 +486,7 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
             const int jend = split ? n : M;
             for (int j = tid; j < jend; j += nt, rotj = cmul(rotj, rstep)) {
                 CR v = zero;
-                const int k = blu ? (int)brev(j, logM) : j;           // slot of logical index j
+                const int k = blu ? perm(j, L) : j;           // slot of logical index j
                 if (j < n) {
                     CR cn = zero, cs = zero;
                     const int w = (j + mmax) / n;
@@ -458,9 +517,9 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
             split_ring(f, moff);
         } else if (synth) {
             idft_core<R>(buf, L, A);
-            // now x_j (packed N + i S) = conj(buf[brev(j)] * chirp_j)
+            // now x_j (packed N + i S) = conj(buf[perm(j)] * chirp_j)
             for (int j = tid; j < n; j += nt) {
-                const int q = (int)brev(j, logM);
+                const int q = perm(j, L);
                 CR y = buf[pidx(q, sh)];
                 if (L.bluestein) y = cmul(y, chirp[j]);
                 const double xn = (double)y.x, xs = -(double)y.y;
@@ -485,13 +544,13 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
                 }
             }
             if (MODE == RING_ITERATE && L.bluestein) {
-                for (int j = n + tid; j < M; j += nt) buf[pidx((int)brev(j, logM), sh)] = zero;
+                for (int j = n + tid; j < M; j += nt) buf[pidx(perm(j, L), sh)] = zero;
             }
             __syncthreads();
         }
         if ((MODE == RING_ANALYSIS || MODE == RING_ANALYSIS6) && !split) {
             // lanes take consecutive pixels j (coalesced reads); a_j goes to
-            // the bit-reversed slot
+            // the digit-reversed slot perm(j)
             for (int j = tid; j < M; j += nt) {
                 CR a = zero;
                 if (j < n) {
@@ -499,7 +558,7 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
                     a.y = P_.has_s ? (R)in_val(f, moff, P_.off_s + j) : R(0);
                     if (L.bluestein) a = cmul(a, chirp[j]);
                 }
-                buf[pidx((int)brev(j, logM), sh)] = a;
+                buf[pidx(perm(j, L), sh)] = a;
             }
             __syncthreads();
         }
@@ -509,8 +568,8 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
             auto unfold = [&](int m, CR rot) {
                 const int k = m % n;
                 const int k2 = (n - k) % n;
-                const int q1 = blu ? (int)brev(k, logM) : k;
-                const int q2 = blu ? (int)brev(k2, logM) : k2;
+                const int q1 = blu ? perm(k, L) : k;
+                const int q2 = blu ? perm(k2, L) : k2;
                 CR z1 = buf[pidx(q1, shn)], z2 = buf[pidx(q2, shn)];
                 if (blu) { z1 = cmul(z1, chirp[k]); z2 = cmul(z2, chirp[k2]); }
                 const CR xn = mk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
@@ -529,7 +588,7 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
 }
 
 template <typename R>
-RingArgs<R> ring_args(dm_plan* p, const void* chirp, const void* bhat, const void* tw) {
+RingArgs<R> ring_args(dm_plan* p, const void* chirp, const void* bhat, const void* tw, const void* tw3) {
     RingArgs<R> A;
     A.npairs = p->npairs;
     A.plist = nullptr;
@@ -544,6 +603,8 @@ RingArgs<R> ring_args(dm_plan* p, const void* chirp, const void* bhat, const voi
     A.chirp = reinterpret_cast<const C2<R>*>(chirp);
     A.bhat = reinterpret_cast<const C2<R>*>(bhat);
     A.tw = reinterpret_cast<const C2<R>*>(tw);
+    A.tw3 = reinterpret_cast<const C2<R>*>(tw3);
+    A.P3max = p->fft.P3max;
     return A;
 }
 
@@ -555,7 +616,8 @@ void launch_mode(const RingArgs<R>& A, int nlist, const int* plist, int lds_elem
     Ar.plist = plist;
     Ar.nlist = nlist;
     const dim3 grid((unsigned)(((nlist + 7) / 8) * 8 * A.nrhs));
-    const size_t lds = (size_t)(lds_elems + lds_elems / 8 + 8) * sizeof(C2<R>);
+    // padded layout: up to M + M/8 + 24 elements for M = 3 2^k (pidx)
+    const size_t lds = (size_t)(lds_elems + lds_elems / 8 + 32) * sizeof(C2<R>);
     hipLaunchKernelGGL((ring_kernel<MODE, SPLITK, R, P>), grid, dim3(threads), lds, s, Ar, map_in, map_out, K, b, ph);
 }
 
@@ -639,13 +701,13 @@ hipError_t set_lds_t(size_t bytes) {
 hipError_t launch_ring(dm_plan* p, int mode, int nrhs, const double* map_in, double* map_out, const double* K,
                        const double* b, void* phase, bool phase32, hipStream_t s) {
     if (!phase32) {
-        const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw);
+        const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw, p->d_tw3);
         launch_ring_t<double, double>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
     } else if (p->d_tw32) {
-        const RingArgs<float> A = ring_args<float>(p, p->d_chirp32, p->d_bhat32, p->d_tw32);
+        const RingArgs<float> A = ring_args<float>(p, p->d_chirp32, p->d_bhat32, p->d_tw32, p->d_tw332);
         launch_ring_t<float, float>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
     } else {
-        const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw);
+        const RingArgs<double> A = ring_args<double>(p, p->d_chirp, p->d_bhat, p->d_tw, p->d_tw3);
         launch_ring_t<double, float>(p, mode, nrhs, map_in, map_out, K, b, phase, A, s);
     }
     return hipGetLastError();

@@ -249,6 +249,39 @@ static int ilog2(int v) {
     return r;
 }
 
+// DFT of length 3 P (P a power of two) by decimation in time:
+// X[k1 + P k2] = sum_n2 W_3^{n2 k2} W_{3P}^{n2 k1} FFT_P(a[3 n1 + n2])[k1]
+static void fft3_ld(std::vector<std::complex<ld>>& a) {
+    const int M = (int)a.size(), P = M / 3;
+    std::vector<std::complex<ld>> y[3];
+    for (int r = 0; r < 3; ++r) {
+        y[r].resize(P);
+        for (int q = 0; q < P; ++q) y[r][q] = a[3 * q + r];
+        fft_ld(y[r]);
+    }
+    for (int k1 = 0; k1 < P; ++k1)
+        for (int k2 = 0; k2 < 3; ++k2) {
+            std::complex<ld> s(0, 0);
+            for (int r = 0; r < 3; ++r) {
+                const ld ang = -2 * kPi * (ld)((int64_t)r * (k1 + (int64_t)P * k2) % M) / M;
+                s += y[r][k1] * std::complex<ld>(cosl(ang), sinl(ang));
+            }
+            a[k1 + P * k2] = s;
+        }
+}
+
+// the transform size of a length: n itself for 2^k and (from 24 on) 3 2^k;
+// for Bluestein the smaller of the power of two and of 3 2^k (k >= 3) that
+// holds 2n - 1 points
+static bool pow2_len(int n) { return (n & (n - 1)) == 0; }
+static bool r3_len(int n) { return n >= 24 && n % 3 == 0 && pow2_len(n / 3); }
+static int blue_size(int n) {
+    const int m2 = 1 << ilog2(2 * n - 1);
+    int m3 = 24;
+    while (m3 < 2 * n - 1) m3 *= 2;
+    return std::min(m2, m3);
+}
+
 // A Bluestein length n = 4 i is split into four length-i DFTs when its own
 // Bluestein buffer (a power of two >= 2n - 1) exceeds max_elems, the
 // largest buffer one workgroup's LDS holds: the split needs max(n, M_i)
@@ -259,24 +292,30 @@ bool build_fft_tables(const RingTables& rt, int mmax, int max_elems, FftTables& 
     std::vector<int> lens(rt.nphi.begin(), rt.nphi.end());
     std::sort(lens.begin(), lens.end());
     lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
-    auto blue = [](int v) { return 1 << ilog2(2 * v - 1); };
+    // a split length's quarter keeps a power-of-two Bluestein size (its
+    // launch stages four of them in one buffer)
+    auto blue2 = [](int v) { return 1 << ilog2(2 * v - 1); };
     int64_t coff = 0, boff = 0;
     for (int n : lens) {
-        const bool pow2 = (n & (n - 1)) == 0;
-        const bool split = !pow2 && n % 4 == 0 && blue(n) > max_elems;
+        const bool direct = pow2_len(n) || r3_len(n);
+        const bool split = !direct && n % 4 == 0 && blue_size(n) > max_elems;
         const int nb = split ? n / 4 : n;              // Bluestein length
-        const int M = pow2 ? n : blue(nb);
+        const int M = direct ? n : split ? blue2(nb) : blue_size(nb);
+        const int r3 = (M % 3 == 0) ? 1 : 0;
+        const int P = r3 ? M / 3 : M;
         ft.n.push_back(n);
         ft.split.push_back(split ? 1 : 0);
         ft.M.push_back(M);
-        ft.logM.push_back(ilog2(M));
-        ft.chirp_off.push_back(pow2 ? -1 : coff);
-        ft.bhat_off.push_back(pow2 ? -1 : boff);
-        if (!pow2) {
+        ft.logM.push_back(ilog2(P));
+        ft.r3.push_back(r3);
+        ft.chirp_off.push_back(direct ? -1 : coff);
+        ft.bhat_off.push_back(direct ? -1 : boff);
+        if (!direct) {
             coff += nb;
             boff += M;
         }
-        ft.Mmax = std::max(ft.Mmax, M);
+        ft.Mmax = std::max(ft.Mmax, P);
+        if (r3) ft.P3max = std::max(ft.P3max, P);
         if (split)
             ft.lds_split = std::max(ft.lds_split, std::max(n, M));
         else
@@ -299,7 +338,8 @@ bool build_fft_tables(const RingTables& rt, int mmax, int max_elems, FftTables& 
                 b[j] = bj;
                 if (j > 0) b[M - j] = bj;
             }
-            fft_ld(b);
+            if (ft.r3[i]) fft3_ld(b);
+            else fft_ld(b);
             for (int k = 0; k < M; ++k) {
                 ft.bhat[2 * (ft.bhat_off[i] + k)] = (double)(b[k].real() / M);
                 ft.bhat[2 * (ft.bhat_off[i] + k) + 1] = (double)(b[k].imag() / M);
@@ -319,6 +359,15 @@ bool build_fft_tables(const RingTables& rt, int mmax, int max_elems, FftTables& 
     if (ft.Mmax < 2) {
         ft.tw.assign(2, 0.0);
         ft.tw[0] = 1.0;
+    }
+    // the radix-3 passes' twiddles W_{3P}^e = exp(-2 pi i e P3max / (3 P3max P))
+    // for e < 2P, read at stride P3max / P
+    const int n3 = 3 * ft.P3max;
+    ft.tw3.assign(2 * (size_t)n3, 0.0);
+    for (int e = 0; e < n3; ++e) {
+        const ld ang = -2 * kPi * e / n3;
+        ft.tw3[2 * e] = (double)cosl(ang);
+        ft.tw3[2 * e + 1] = (double)sinl(ang);
     }
     (void)err;
     return true;
