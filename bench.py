@@ -115,9 +115,13 @@ def traffic_from_csv(fetch_csv, write_csv, prec, nrhs, command, last):
     fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
 
     def find(acc, key, per):
+        # the ring step runs once per iteration but the last: a solve of k
+        # iterations has k - 1 of them, so the ring keeps 2/3 as many steps
+        # as the Legendre kernels keep launches (two 3-iteration solves)
+        steps = last if per == 1 else max(1, last * 2 // 3)
         for name, d in acc.items():
             if key in name:
-                v = [x for _, x in sorted(d.items(), key=lambda kv: int(kv[0]))][-last * per:]
+                v = [x for _, x in sorted(d.items(), key=lambda kv: int(kv[0]))][-steps * per:]
                 return [sum(v[i:i + per]) for i in range(0, len(v) - per + 1, per)]
         return []
 
