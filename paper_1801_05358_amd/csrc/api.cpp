@@ -228,8 +228,8 @@ void leg_analysis(dm_plan* p, int nrhs, bool weighted, const double* filter, dou
     // every Legendre kernel (vector and matrix-core) carries the scaled
     // recursions mu = lam / S: the scales multiply the partial sums here and
     // the spin-basis copy the synthesis reads
-    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, partial32, filter, alm, spin, cpart, p->d_scale,
-                          s));
+    HIPCHK(launch_combine(p, nrhs, nslots, p->d_partial, partial32, use_mfma(p, nrhs) ? p->d_slot_lo : nullptr,
+                          filter, alm, spin, cpart, p->d_scale, s));
     t.done();
 }
 
@@ -909,7 +909,7 @@ void free_plan(dm_plan* p) {
     dfree(p->d_plist_whole); dfree(p->d_plist_split); dfree(p->d_plist_small); dfree(p->d_plist_big);
     dfree(p->d_chirp); dfree(p->d_bhat); dfree(p->d_tw);
     dfree(p->d_tw3); dfree(p->d_tw332);
-    dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_coef_s); dfree(p->d_scale); dfree(p->d_lstart); dfree(p->d_seed);
+    dfree(p->d_chirp32); dfree(p->d_bhat32); dfree(p->d_tw32); dfree(p->d_coef); dfree(p->d_coef_s); dfree(p->d_scale); dfree(p->d_lstart); dfree(p->d_slot_lo); dfree(p->d_seed);
     dfree(p->d_lp0); dfree(p->d_lp2); dfree(p->d_K); dfree(p->d_tn); dfree(p->d_ninv); dfree(p->d_obs);
     dfree(p->d_ninv6); dfree(p->d_tn6); dfree(p->d_state_u);
     dfree(p->d_ring_w); dfree(p->d_ring_off); dfree(p->d_ring_n); dfree(p->d_phase); dfree(p->d_phase32); dfree(p->d_partial);
@@ -1167,6 +1167,8 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         dalloc(p, p->d_lstart, sn);
         dalloc(p, p->d_seed, sn * kSeedFields);
         HIPCHK(launch_seeds(p, p->stream));
+        dalloc(p, p->d_slot_lo, (size_t)(p->mmax + 1) * batched_analysis_slots(p));
+        HIPCHK(launch_slot_starts(p, p->d_slot_lo, p->stream));
 
         // tiling of the Legendre kernels (ring pairs per lane R); the
         // DMWF_ANA_R / DMWF_SYN_R / DMWF_SYN_THREADS / DMWF_*_MCHUNK

@@ -109,6 +109,7 @@ struct dm_plan {
     double* d_coef_s = nullptr;        // [nalm][kCoefSStride] scaled recursions (batched kernels)
     double* d_scale = nullptr;         // [nalm][2] their scales S (spin 0, spin 2)
     int* d_lstart = nullptr;           // [mmax+1][npairs]
+    int* d_slot_lo = nullptr;          // [mmax+1][batched analysis slots]: first start degree per slot
     double* d_seed = nullptr;          // [kSeedFields][mmax+1][npairs]
     double* d_lp0 = nullptr;           // [mmax+1] log seed prefactors, spin 0
     double* d_lp2 = nullptr;           // [mmax+1] log seed prefactors, spin 2
@@ -270,10 +271,11 @@ hipError_t launch_leg_analysis(dm_plan* p, int nrhs, const double* phase, const 
                                double* partial, hipStream_t s);
 // scale (nullable): the batched kernels' recursion scales, applied to the
 // partial sums and to the spin-basis copy; partial32: the slots hold FP32
-// (the mixed batched analysis), else FP64
+// (the mixed batched analysis), else FP64; slot_lo (nullable, [mmax+1][nslots]):
+// slot c holds degrees l >= slot_lo[m][c] only (the batched analysis)
 hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, bool partial32,
-                          const double* filter, double* alm, double* spin, double* cpart, const double* scale,
-                          hipStream_t s);
+                          const int* slot_lo, const double* filter, double* alm, double* spin, double* cpart,
+                          const double* scale, hipStream_t s);
 int64_t cauchy_blocks(dm_plan* p);   // Cauchy partial sums per RHS written by the combine kernel
 hipError_t launch_cauchy_reduce(dm_plan* p, int nrhs, const double* cpart, double* out, hipStream_t s);
 hipError_t launch_to_spin(dm_plan* p, int nrhs, const double* alm, double* spin, const double* scale,
@@ -284,6 +286,8 @@ void set_analysis_tiling(dm_plan* p, int R);
 // (FP64 for DM_FP64 plans, FP32 for DM_MIXED); analysis writes one
 // partial-sum slot per block of ring pairs
 int batched_analysis_slots(dm_plan* p);
+// the first start degree of each (m, slot) from the plan's start degrees
+hipError_t launch_slot_starts(dm_plan* p, int* slot_lo, hipStream_t s);
 // batched kernels: phase is FP32 ring data for DM_MIXED, FP64 otherwise
 hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, void* phase, hipStream_t s);
 hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pair_w, double* partial,

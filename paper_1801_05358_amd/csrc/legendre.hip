@@ -580,6 +580,7 @@ __global__ __launch_bounds__(256) void cauchy_reduce_kernel(const double* __rest
 template <typename PV>
 __global__ __launch_bounds__(256) void combine_kernel(int lmax, int lend, int64_t nalm, int nchunks, int nrhs,
                                                       const PV* __restrict__ partial,
+                                                      const int* __restrict__ slot_lo,
                                                       const double* __restrict__ filt, double2* __restrict__ alm,
                                                       double2* __restrict__ spin, double* __restrict__ cpart,
                                                       const double* __restrict__ scale) {
@@ -596,6 +597,8 @@ __global__ __launch_bounds__(256) void combine_kernel(int lmax, int lend, int64_
         for (int f = 0; f < 3; ++f) {
             double2 s = make_double2(0.0, 0.0);
             for (int c = 0; c < nc; ++c) {
+                // a slot holds degrees from its first start degree on
+                if (slot_lo && l < slot_lo[(int64_t)m * nchunks + c]) continue;
                 const PV v = partial[(((int64_t)c * nrhs + rhs) * 3 + f) * nalm + idx];
                 s.x += (double)v.x;
                 s.y += (double)v.y;
@@ -716,17 +719,17 @@ void set_analysis_tiling(dm_plan* p, int R) {
 }
 
 hipError_t launch_combine(dm_plan* p, int nrhs, int nslots, const double* partial, bool partial32,
-                          const double* filter, double* alm, double* spin, double* cpart, const double* scale,
-                          hipStream_t s) {
+                          const int* slot_lo, const double* filter, double* alm, double* spin, double* cpart,
+                          const double* scale, hipStream_t s) {
     dim3 grid((p->lmax + 1 + 255) / 256, p->mmax + 1, nrhs);
     const int lend = (p->lcut > 0 && p->lcut < p->lmax) ? p->lcut : p->lmax;
     if (partial32)
         hipLaunchKernelGGL(combine_kernel<float2>, grid, dim3(256), 0, s, p->lmax, lend, p->nalm, nslots, nrhs,
-                           reinterpret_cast<const float2*>(partial), filter, reinterpret_cast<double2*>(alm),
+                           reinterpret_cast<const float2*>(partial), slot_lo, filter, reinterpret_cast<double2*>(alm),
                            reinterpret_cast<double2*>(spin), cpart, scale);
     else
         hipLaunchKernelGGL(combine_kernel<double2>, grid, dim3(256), 0, s, p->lmax, lend, p->nalm, nslots, nrhs,
-                           reinterpret_cast<const double2*>(partial), filter, reinterpret_cast<double2*>(alm),
+                           reinterpret_cast<const double2*>(partial), slot_lo, filter, reinterpret_cast<double2*>(alm),
                            reinterpret_cast<double2*>(spin), cpart, scale);
     return hipGetLastError();
 }

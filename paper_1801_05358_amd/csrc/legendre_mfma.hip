@@ -511,7 +511,7 @@ __device__ __forceinline__ void rec_act(const BatchArgs& A, const double* __rest
 // PT: the partial-sum slots' type (FP32 on the mixed path, where the
 // products are FP32 already; the combine kernel sums the slots in FP64)
 template <typename T, int W, typename PT>
-__global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typename Vec2<T>::t* __restrict__ phase,
+__global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(BatchArgs A, const typename Vec2<T>::t* __restrict__ phase,
                                                       const double* __restrict__ pair_w,
                                                       PT* __restrict__ partial) {
     typedef typename Mfma<T>::v4 v4;
@@ -538,6 +538,10 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
     int lo = wave_min(s.ls);
     int hi = wave_max(s.ls <= lmax ? s.ls : 0);
     if (lane == 0) { s_lo[wv] = lo; s_hi[wv] = hi; }
+    // the wave's own last start degree: past it, its rounds need no
+    // activation even while other waves of the block still start
+    int hi_w = __builtin_amdgcn_readfirstlane(hi);
+    if (m < 2) hi_w = max(hi_w, 2);
 
     // B operands: K step st < KH takes the north ring of pair 4 st + k,
     // st >= KH the mirror ring of pair 4 (st - KH) + k; col = (rhs, re/im);
@@ -573,17 +577,8 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
 
     const int nrhs = A.nrhs;
     PT* out = partial + ((int64_t)bp.x * nrhs * 3) * A.nalm * 2;
-    const int ncol = min(8, nrhs - rb);
-    // degrees below the block's first active one: zero partial sums
-    // (consecutive threads write consecutive (l, re/im))
-    {
-        const int nl = min(lo, lend + 1) - m;
-        const int run = 2 * nl, total = run * 3 * ncol;
-        for (int q = threadIdx.x; q < total; q += 64 * W) {
-            const int fr = q / run, w = q - fr * run;           // fr = rhs * 3 + f within the tile
-            out[((int64_t)(rb * 3 + fr) * A.nalm + base + m) * 2 + w] = (PT)0;
-        }
-    }
+    // degrees below the block's first start degree lo are not written: the
+    // combine kernel reads this slot from lo on (the slot start table)
     if (lo > lend) return;
 
     T* tl = tile[wv];
@@ -687,7 +682,14 @@ __global__ __launch_bounds__(64 * W) void bana_kernel(BatchArgs A, const typenam
         }
         // the products have read the tile (LDS operations of a wave
         // complete in order): the next round's recursion overwrites it
-        if (l0 + 16 <= lend) produce(l0 + 16, q, mode);
+        if constexpr (kMode == 1) {
+            if (l0 + 16 <= lend) {
+                if (l0 + 16 <= hi_w) produce(l0 + 16, q, mode);
+                else produce(l0 + 16, q, std::integral_constant<int, 0>());
+            }
+        } else {
+            if (l0 + 16 <= lend) produce(l0 + 16, q, mode);
+        }
         if (l0 > lo) reduce(l0 - 16, q ^ 1);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -723,16 +725,43 @@ BatchArgs batch_args(dm_plan* p, int nrhs) {
     return a;
 }
 
-constexpr int kAnaWaves = 8;
+// waves per analysis block, both precisions: FP32 blocks take 77 KB of LDS
+// and at most 256 registers per lane, so two blocks share a CU and one
+// block's barriers do not stall the other (at Nside 1024, lmax 2048, 8 RHS:
+// 8.8 against 9.7 ms for one block of 8 waves per CU); FP64 blocks take
+// 152 KB, one per CU.  Both group 256 ring pairs per partial-sum slot.
+constexpr int kAnaWaves = 4;
 
 }  // namespace
 
-// FP32 blocks hold 8 waves, FP64 blocks 4 (their LDS tiles are twice as big)
-static int bana_waves(dm_plan* p) { return p->precision == DM_MIXED ? kAnaWaves : kAnaWaves / 2; }
-
 int batched_analysis_slots(dm_plan* p) {
-    const int per = kAnaPW * bana_waves(p);
+    const int per = kAnaPW * kAnaWaves;
     return (p->npairs + per - 1) / per;
+}
+
+namespace {
+
+// first start degree of each (m, partial-sum slot): the smallest start
+// degree of the slot's ring pairs (lmax + 1 if none starts)
+__global__ void slot_start_kernel(int npairs, int per, int nslots, int lmax, const int* __restrict__ lstart,
+                                  int* __restrict__ slot_lo) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (x >= nslots) return;
+    int lo = lmax + 1;
+    const int p1 = min(npairs, (x + 1) * per);
+    for (int p = x * per; p < p1; ++p) lo = min(lo, lstart[(int64_t)m * npairs + p]);
+    slot_lo[(int64_t)m * nslots + x] = lo;
+}
+
+}  // namespace
+
+hipError_t launch_slot_starts(dm_plan* p, int* slot_lo, hipStream_t s) {
+    const int nslots = batched_analysis_slots(p);
+    dim3 grid((nslots + 63) / 64, p->mmax + 1);
+    hipLaunchKernelGGL(slot_start_kernel, grid, dim3(64), 0, s, p->npairs, kAnaPW * kAnaWaves, nslots, p->lmax,
+                       p->d_lstart, slot_lo);
+    return hipGetLastError();
 }
 
 template <int W>
@@ -768,7 +797,7 @@ hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pa
         hipLaunchKernelGGL((bana_kernel<float, kAnaWaves, float>), grid, dim3(64 * kAnaWaves), 0, s, A,
                            static_cast<const float2*>(phase), pair_w, reinterpret_cast<float*>(partial));
     else
-        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves / 2, double>), grid, dim3(32 * kAnaWaves), 0, s, A,
+        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves, double>), grid, dim3(64 * kAnaWaves), 0, s, A,
                            static_cast<const double2*>(phase), pair_w, partial);
     return hipGetLastError();
 }
