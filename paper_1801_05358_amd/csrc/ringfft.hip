@@ -132,45 +132,76 @@ __device__ __forceinline__ C2<R> root_mul(C2<R> w, int r, int t, bool inv) {
     return cmul(w, z);
 }
 
+// one group of a pass: the 2^G elements at slots at[c], stages s .. s+G-1
+template <typename R, int G, bool DIT>
+__device__ __forceinline__ void fft_group(C2<R>* buf, const int (&at)[1 << G], int j, int s, int logMmax,
+                                          const C2<R>* __restrict__ tw, bool inv) {
+    constexpr int NG = 1 << G;
+    C2<R> x[NG];
+#pragma unroll
+    for (int c = 0; c < NG; ++c) x[c] = buf[at[c]];
+    C2<R> wb[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        wb[t] = tw[j << (logMmax - s - t - 1)];
+        if (inv) wb[t].y = -wb[t].y;
+    }
+#pragma unroll
+    for (int tt = 0; tt < G; ++tt) {
+        const int t = DIT ? tt : G - 1 - tt;
+        const int half = 1 << t;
+#pragma unroll
+        for (int c = 0; c < NG; ++c) {
+            if (c & half) continue;
+            const C2<R> w = root_mul<R>(wb[t], c & (half - 1), t, inv);
+            const C2<R> a = x[c], b = x[c + half];
+            if (DIT) {
+                const C2<R> bw = cmul(b, w);
+                x[c] = mk<R>(a.x + bw.x, a.y + bw.y);
+                x[c + half] = mk<R>(a.x - bw.x, a.y - bw.y);
+            } else {
+                x[c] = mk<R>(a.x + b.x, a.y + b.y);
+                x[c + half] = cmul(mk<R>(a.x - b.x, a.y - b.y), w);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NG; ++c) buf[at[c]] = x[c];
+}
+
+// The slots of a group's elements base + c h are pidx(base) + c step, with
+// step = h + h/8 + h/2^sh, whenever neither shift of pidx carries across the
+// group: s >= 3 or s + G <= 3 for i/8, and s >= sh or s + G <= sh for
+// i/2^sh.  That holds for every pass of the transforms below but at most
+// one per transform (the pass that straddles bit sh); those passes take
+// pidx per element, the others one add per element.
 template <typename R, int G, bool DIT>
 __device__ __forceinline__ void fft_pass(C2<R>* buf, int M, int sh, int s, int logMmax,
                                          const C2<R>* __restrict__ tw, bool inv) {
     constexpr int NG = 1 << G;
     const int h = 1 << s;
     const int ngroups = M >> G;
-    for (int q = threadIdx.x; q < ngroups; q += blockDim.x) {
-        const int j = q & (h - 1);
-        const int base = ((q >> s) << (s + G)) + j;
-        C2<R> x[NG];
+    const bool lin = (s >= 3 || s + G <= 3) && (s >= sh || s + G <= sh);
+    const int step = h + (h >> 3) + (h >> sh);
+    if (lin) {
+        for (int q = threadIdx.x; q < ngroups; q += blockDim.x) {
+            const int j = q & (h - 1);
+            const int base = ((q >> s) << (s + G)) + j;
+            int at[NG];
+            at[0] = pidx(base, sh);
 #pragma unroll
-        for (int c = 0; c < NG; ++c) x[c] = buf[pidx(base + c * h, sh)];
-        C2<R> wb[G];
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-            wb[t] = tw[j << (logMmax - s - t - 1)];
-            if (inv) wb[t].y = -wb[t].y;
+            for (int c = 1; c < NG; ++c) at[c] = at[c - 1] + step;
+            fft_group<R, G, DIT>(buf, at, j, s, logMmax, tw, inv);
         }
+    } else {
+        for (int q = threadIdx.x; q < ngroups; q += blockDim.x) {
+            const int j = q & (h - 1);
+            const int base = ((q >> s) << (s + G)) + j;
+            int at[NG];
 #pragma unroll
-        for (int tt = 0; tt < G; ++tt) {
-            const int t = DIT ? tt : G - 1 - tt;
-            const int half = 1 << t;
-#pragma unroll
-            for (int c = 0; c < NG; ++c) {
-                if (c & half) continue;
-                const C2<R> w = root_mul<R>(wb[t], c & (half - 1), t, inv);
-                const C2<R> a = x[c], b = x[c + half];
-                if (DIT) {
-                    const C2<R> bw = cmul(b, w);
-                    x[c] = mk<R>(a.x + bw.x, a.y + bw.y);
-                    x[c + half] = mk<R>(a.x - bw.x, a.y - bw.y);
-                } else {
-                    x[c] = mk<R>(a.x + b.x, a.y + b.y);
-                    x[c + half] = cmul(mk<R>(a.x - b.x, a.y - b.y), w);
-                }
-            }
+            for (int c = 0; c < NG; ++c) at[c] = pidx(base + c * h, sh);
+            fft_group<R, G, DIT>(buf, at, j, s, logMmax, tw, inv);
         }
-#pragma unroll
-        for (int c = 0; c < NG; ++c) buf[pidx(base + c * h, sh)] = x[c];
     }
     __syncthreads();
 }
@@ -189,10 +220,12 @@ __device__ void fft_dit(C2<R>* buf, int M, int logM, int logMmax, const C2<R>* _
 template <typename R>
 __device__ void fft_dif(C2<R>* buf, int M, int logM, int logMmax, const C2<R>* __restrict__ tw, bool inv) {
     const int sh = pad_shift(logM);
+    // the stages that do not fill a radix-8 pass first, so that the radix-8
+    // passes sit at s = 0, 3, 6, ... (as in the DIT transform)
     int top = logM;
+    if (logM % 3 == 2) fft_pass<R, 2, false>(buf, M, sh, top - 2, logMmax, tw, inv), top -= 2;
+    else if (logM % 3 == 1) fft_pass<R, 1, false>(buf, M, sh, top - 1, logMmax, tw, inv), top -= 1;
     for (; top >= 3; top -= 3) fft_pass<R, 3, false>(buf, M, sh, top - 3, logMmax, tw, inv);
-    if (top == 2) fft_pass<R, 2, false>(buf, M, sh, 0, logMmax, tw, inv);
-    else if (top == 1) fft_pass<R, 1, false>(buf, M, sh, 0, logMmax, tw, inv);
 }
 
 // The radix-3 pass of a size M = 3 P: elements k, P + k, 2P + k for
@@ -205,12 +238,16 @@ __device__ void fft_dif(C2<R>* buf, int M, int logM, int logMmax, const C2<R>* _
 template <typename R, bool DIT>
 __device__ void r3_pass(C2<R>* buf, int P, int sh, const C2<R>* __restrict__ tw3, int P3max, bool inv) {
     const int st = P3max / P;
+    const int Ps = P + (P >> 3) + (P >> sh);
     const R h = R(0.86602540378443864676);          // sin(2 pi / 3)
     const R sg = inv ? R(-1) : R(1);
     for (int k = threadIdx.x; k < P; k += blockDim.x) {
         C2<R> w1 = tw3[k * st], w2 = tw3[2 * k * st];
         if (inv) { w1.y = -w1.y; w2.y = -w2.y; }
-        C2<R> x0 = buf[pidx(k, sh)], x1 = buf[pidx(P + k, sh)], x2 = buf[pidx(2 * P + k, sh)];
+        // P = 2^k with k >= 3 is a multiple of 8 and of 2^sh: the slots of k, P + k, 2P + k
+        // are pidx(k) + {0, 1, 2} (P + P/8 + P/2^sh)
+        const int a0 = pidx(k, sh), a1 = a0 + Ps, a2 = a1 + Ps;
+        C2<R> x0 = buf[a0], x1 = buf[a1], x2 = buf[a2];
         if (DIT) { x1 = cmul(x1, w1); x2 = cmul(x2, w2); }
         const C2<R> t1 = mk<R>(x1.x + x2.x, x1.y + x2.y), t2 = mk<R>(x1.x - x2.x, x1.y - x2.y);
         const C2<R> mid = mk<R>(x0.x - R(0.5) * t1.x, x0.y - R(0.5) * t1.y);
@@ -218,9 +255,9 @@ __device__ void r3_pass(C2<R>* buf, int P, int sh, const C2<R>* __restrict__ tw3
         const C2<R> it = mk<R>(sg * h * t2.y, -sg * h * t2.x);
         C2<R> y1 = mk<R>(mid.x + it.x, mid.y + it.y), y2 = mk<R>(mid.x - it.x, mid.y - it.y);
         if (!DIT) { y1 = cmul(y1, w1); y2 = cmul(y2, w2); }
-        buf[pidx(k, sh)] = mk<R>(x0.x + t1.x, x0.y + t1.y);
-        buf[pidx(P + k, sh)] = y1;
-        buf[pidx(2 * P + k, sh)] = y2;
+        buf[a0] = mk<R>(x0.x + t1.x, x0.y + t1.y);
+        buf[a1] = y1;
+        buf[a2] = y2;
     }
     __syncthreads();
 }
