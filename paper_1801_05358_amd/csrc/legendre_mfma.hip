@@ -623,13 +623,16 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
     for (int v = 0; v < 4; ++v) sg[v] = ((lo + Mfma<T>::row(lane, v) + m) & 1) ? (T)-1 : (T)1;
 
     // sum over the waves (FP64) of the round that started at degree l0,
-    // held in red[qb], into the block's slot; thread t takes re/im t & 1,
-    // degree (t >> 1) & 15 and (rhs, f) t >> 5, so that each run of 32
-    // threads writes 256 contiguous bytes
+    // held in red[qb], into the block's slot; element e of the round's
+    // 3 x 8 x 16 x 2 outputs is re/im e & 1, degree (e >> 1) & 15, rhs
+    // (e >> 5) & 7 and field e >> 8, so that each run of 32 threads writes
+    // 128 contiguous bytes and a thread's fields are compile-time constants
+    static_assert(768 % (64 * W) == 0, "the round's outputs split evenly over the block");
     auto reduce = [&](int l0, int qb) {
-        for (int e = threadIdx.x; e < 3 * 256; e += 64 * W) {
-            const int ri2 = e & 1, r = (e >> 1) & 15, fr = e >> 5;
-            const int rr = fr / 3, f = fr - 3 * rr;
+#pragma unroll
+        for (int k = 0; k < 768 / (64 * W); ++k) {
+            const int e = threadIdx.x + k * 64 * W;
+            const int ri2 = e & 1, r = (e >> 1) & 15, rr = (e >> 5) & 7, f = e >> 8;
             const int ofs = f * kRedF + (2 * rr + ri2) * kRedCol + r;
             double sum = 0.0;
 #pragma unroll
