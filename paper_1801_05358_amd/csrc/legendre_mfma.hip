@@ -393,16 +393,22 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
             // l0 + 7) to LDS slot 0, the next group in flight
             cofw[wv][0][lane] = coef_fetch(cf, l0 + 4, lmax, lane, 4);
             double creg = coef_fetch(cf, l0 + 8, lmax, lane, 4);
+            // B operands of the next round (degree l0 + 4 + k <= lend: no
+            // clamp), one pointer advanced by 4 degrees per round
+            const double* __restrict__ bq = sbase + (int64_t)(l0 + 4 + k) * 2;
+            const int64_t fst = A.nalm * 2;
             wave_sync();
             int cs = 0;
-            for (; l0 + 7 <= lend; l0 += 4, q ^= 1, cs ^= 1) {
+            for (; l0 + 7 <= lend; l0 += 4, q ^= 1, cs ^= 1, bq += 8) {
                 T b[3], bs[3];
                 operands(braw, b, bs);
                 // the in-flight group (degrees l0 + 8 ..) to the other slot,
                 // then the group after it, then the next B operands
                 cofw[wv][cs ^ 1][lane] = creg;
                 creg = coef_fetch(cf, l0 + 12, lmax, lane, 4);
-                load_b(l0 + 4 + k, braw);
+                braw[0] = bq[0];
+                braw[1] = bq[fst];
+                braw[2] = bq[2 * fst];
                 bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {

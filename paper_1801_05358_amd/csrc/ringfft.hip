@@ -101,6 +101,13 @@ __device__ __forceinline__ int perm(int j, const FftLenDev& L) {
     return (int)brev((unsigned)j, L.logM);
 }
 
+// logical index held by slot k (the inverse of perm): brev(k), or for
+// M = 3 P, k = d P + e, the index 3 brev(e) + d
+__device__ __forceinline__ int perm_inv(int k, const FftLenDev& L) {
+    if (L.r3) return 3 * (int)brev((unsigned)(k & ((L.M / 3) - 1)), L.logM) + (k >> L.logM);
+    return (int)brev((unsigned)k, L.logM);
+}
+
 // e^{i m phi0} with phi0 = pi / den (den = 0: phi0 = 0), reduced exactly
 template <typename R>
 __device__ __forceinline__ C2<R> phase_rot(int m, int den) {
@@ -153,8 +160,8 @@ __device__ __forceinline__ void fft_group(C2<R>* buf, const int (&at)[1 << G], i
 #pragma unroll
         for (int c = 0; c < NG; ++c) {
             if (c & half) continue;
-            const C2<R> w = root_mul<R>(wb[t], c & (half - 1), t, inv);
             const C2<R> a = x[c], b = x[c + half];
+            const C2<R> w = root_mul<R>(wb[t], c & (half - 1), t, inv);
             if (DIT) {
                 const C2<R> bw = cmul(b, w);
                 x[c] = mk<R>(a.x + bw.x, a.y + bw.y);
@@ -520,11 +527,10 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
             const bool half_turn = P_.phi0_den == n;
             CR rotj = phase_rot<R>(tid, P_.phi0_den);
             const CR rstep = phase_rot<R>(nt, P_.phi0_den);
-            const int jend = split ? n : M;
-            for (int j = tid; j < jend; j += nt, rotj = cmul(rotj, rstep)) {
+            for (int j = tid; j < n; j += nt, rotj = cmul(rotj, rstep)) {
                 CR v = zero;
                 const int k = blu ? perm(j, L) : j;           // slot of logical index j
-                if (j < n) {
+                {
                     CR cn = zero, cs = zero;
                     const int w = (j + mmax) / n;
                     const int mstart = j - n * w;
@@ -548,6 +554,10 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
                 }
                 buf[pidx(k, shn)] = v;
             }
+            // Bluestein: zeros in the slots of the indices n .. M-1
+            if (blu)
+                for (int k = tid; k < M; k += nt)
+                    if (perm_inv(k, L) >= n) buf[pidx(k, sh)] = zero;
             __syncthreads();
         }
         if constexpr (split) {
@@ -581,22 +591,24 @@ __global__ __launch_bounds__(SPLITK > 0 ? 512 : 1024) void ring_kernel(RingArgs<
                 }
             }
             if (MODE == RING_ITERATE && L.bluestein) {
-                for (int j = n + tid; j < M; j += nt) buf[pidx(perm(j, L), sh)] = zero;
+                for (int k = tid; k < M; k += nt)
+                    if (perm_inv(k, L) >= n) buf[pidx(k, sh)] = zero;
             }
             __syncthreads();
         }
         if ((MODE == RING_ANALYSIS || MODE == RING_ANALYSIS6) && !split) {
             // lanes take consecutive pixels j (coalesced reads); a_j goes to
             // the digit-reversed slot perm(j)
-            for (int j = tid; j < M; j += nt) {
-                CR a = zero;
-                if (j < n) {
-                    a.x = (R)in_val(f, moff, P_.off_n + j);
-                    a.y = P_.has_s ? (R)in_val(f, moff, P_.off_s + j) : R(0);
-                    if (L.bluestein) a = cmul(a, chirp[j]);
-                }
+            for (int j = tid; j < n; j += nt) {
+                CR a;
+                a.x = (R)in_val(f, moff, P_.off_n + j);
+                a.y = P_.has_s ? (R)in_val(f, moff, P_.off_s + j) : R(0);
+                if (L.bluestein) a = cmul(a, chirp[j]);
                 buf[pidx(perm(j, L), sh)] = a;
             }
+            if (L.bluestein)
+                for (int k = tid; k < M; k += nt)
+                    if (perm_inv(k, L) >= n) buf[pidx(k, sh)] = zero;
             __syncthreads();
         }
         if (anal) {
