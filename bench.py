@@ -72,6 +72,69 @@ def ring_bytes(npix, nrings, mmax, nrhs, p_ring=8, p_map=8):
     return float(nrhs) * 3 * nrings * (mmax + 1) * 2 * p_ring * 2 + 3.0 * npix * p_map * (1 + nrhs)
 
 
+def _pow2(n):
+    return n & (n - 1) == 0
+
+
+def ring_lds_bytes(nside, mmax, nrhs, max_elems=8192):
+    """LDS bytes (read, written) of one ring step (synthesis, pixel update
+    and analysis of every HEALPix ring pair), in the kernel's own terms:
+    16-byte elements (FP64 complex); a transform of size M = 2^a or 3 2^a
+    runs ceil(a / 3) radix-8 passes (plus one radix-3 pass), each reading
+    and writing the buffer once; the fold writes the buffer, the pixel
+    update reads and writes the ring, the unfold reads two values per m.  A
+    Bluestein length (size rules of the plan's FFT tables: the smaller of
+    2^k and 3 2^k holding 2n - 1 points) takes two transforms and the kernel
+    product per direction, and zero padding after the fold and the update.
+    None when some length would be split (its launch has another layout)."""
+    def r3(n):
+        return n >= 24 and n % 3 == 0 and _pow2(n // 3)
+
+    def blue(n):
+        m2 = 1
+        while m2 < 2 * n - 1:
+            m2 *= 2
+        m3 = 24
+        while m3 < 2 * n - 1:
+            m3 *= 2
+        return min(m2, m3)
+
+    def passes(M):
+        P = M // 3 if M % 3 == 0 else M
+        return (P.bit_length() - 1 + 2) // 3 + (1 if M % 3 == 0 else 0)
+
+    rd = wr = 0
+    for i in range(1, 2 * nside + 1):
+        n = 4 * i if i < nside else 4 * nside
+        direct = _pow2(n) or r3(n)
+        M = n if direct else blue(n)
+        if not direct and M > max_elems:
+            return None
+        pp = passes(M)
+        if direct:
+            r = 2 * pp * M + n + 2 * (mmax + 1)
+            w = n + 2 * pp * M + n
+        else:
+            r = 2 * (2 * pp * M + M) + n + 2 * (mmax + 1)
+            w = M + 2 * (2 * pp * M + M) + n + (M - n)
+        rd += r
+        wr += w
+    f = 16.0 * 3 * nrhs
+    return rd * f, wr * f
+
+
+def lds_rates():
+    """Measured chip-wide LDS read and write rates (bytes/s) of the ring
+    kernel's access pattern, from the committed probe summary."""
+    rec = {}
+    with open(os.path.join(ROOT, "profiles", "lds_bandwidth_mi355x.txt")) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    return float(rec["read_TBps"]) * 1e12, float(rec["write_TBps"]) * 1e12
+
+
 def source_sha(kernel):
     with open(os.path.join(ROOT, "paper_1801_05358_amd", "csrc", KERNEL_SOURCES[kernel]), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -594,6 +657,17 @@ def main():
                          "unit": "GB/s", "frac": round(rb / (ring_ms / max(ring_n, 1) * 1e-3) / 1e9 / HBM_PEAK, 4),
                          "algorithmic_bytes": rb, "traffic": ring_traffic},
     }
+    # the ring step's LDS roofline: its LDS bytes at the measured read and
+    # write rates, against the measured step time
+    lds = ring_lds_bytes(nside, lmax, B)
+    if lds is not None:
+        rr, wr = lds_rates()
+        floor_ms = 1e3 * (lds[0] / rr + lds[1] / wr)
+        step_ms = ring_ms / max(ring_n, 1)
+        rec["ring_fft_lds"] = {"bound": "lds", "read_bytes": lds[0], "write_bytes": lds[1],
+                               "floor_ms": round(floor_ms, 4), "measured_ms": round(step_ms, 4),
+                               "frac": round(floor_ms / step_ms, 4),
+                               "peak": "measured read/write rates, profiles/lds_bandwidth_mi355x.txt"}
 
     if args.adaptive:
         rec["adaptive_resolution"] = {"factor": args.adaptive,

@@ -58,3 +58,19 @@ def test_kernel_summary_keeps_the_last_dispatches(tmp_path):
     assert "# command: cmd" in text and "tiny_kernel" not in text
     last = [l for l in text.splitlines() if l.startswith("void bana_kernel") and l.split()[-2] == "2"]
     assert last and float(last[0].split()[-1]) == 200.0
+
+
+def test_ring_lds_model_counts_passes():
+    """The LDS model of the ring step, by hand at Nside 1 (two ring pairs of
+    4 pixels, one radix-4 pass per transform): per field and pair the fold
+    writes 4 elements, the two transforms read and write 4 each, the update
+    reads and writes 4, the unfold reads 2 (mmax + 1) = 6, at 16 bytes per
+    element, 3 fields.  A split length (a Bluestein size above the LDS
+    buffer, Nside 2048) has no model."""
+    r, w = bench.ring_lds_bytes(1, 2, 1)
+    assert r == 2 * (2 * 4 + 4 + 6) * 16 * 3 and w == 2 * (4 + 2 * 4 + 4) * 16 * 3
+    r, w = bench.ring_lds_bytes(1024, 2048, 8)
+    assert abs(r / 1e9 - 58.39) < 0.01 and abs(w / 1e9 - 59.72) < 0.01
+    assert bench.ring_lds_bytes(2048, 4096, 8) is None
+    rr, wr = bench.lds_rates()
+    assert 1e13 < wr < rr < 2e14
