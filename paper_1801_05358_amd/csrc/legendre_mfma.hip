@@ -178,7 +178,10 @@ constexpr int kCoefN = 3;
 __device__ __forceinline__ double coef_fetch(const double* __restrict__ cf, int l0, int lmax, int t, int G) {
     const int tc = min(t, G * kCoefN - 1);
     const int d = tc / kCoefN, i = tc - d * kCoefN;
-    return cf[(int64_t)min(l0 + d, lmax) * kCoefSStride + i];
+    // a uniform base (cf points at the order's first degree) and a 32-bit
+    // byte offset per lane
+    const unsigned off = (unsigned)((min(l0 + d, lmax) * kCoefSStride + i) * 8);
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(cf) + off);
 }
 
 __device__ __forceinline__ Coef coef_lds(const double* c) { return Coef{c[0], c[1], c[2]}; }
@@ -390,32 +393,52 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
         // steady state: matrix products of this round, recursion of the next
         if (l0 + 7 <= lend) {
             // coefficients of the first steady recursion (degrees l0 + 4 ..
-            // l0 + 7) to LDS slot 0, the next group in flight
-            cofw[wv][0][lane] = coef_fetch(cf, l0 + 4, lmax, lane, 4);
+            // l0 + 7) to LDS slot q (the slot index follows the tile index),
+            // the next group in flight
+            cofw[wv][q][lane] = coef_fetch(cf, l0 + 4, lmax, lane, 4);
             double creg = coef_fetch(cf, l0 + 8, lmax, lane, 4);
             // B operands of the next round (degree l0 + 4 + k <= lend: no
-            // clamp), one pointer advanced by 4 degrees per round
-            const double* __restrict__ bq = sbase + (int64_t)(l0 + 4 + k) * 2;
-            const int64_t fst = A.nalm * 2;
+            // clamp): three uniform field bases and one 32-bit byte offset
+            // per lane, advanced by 4 degrees per round
+            const char* __restrict__ sb0 = reinterpret_cast<const char*>(spin);
+            const int64_t fbytes = A.nalm * 16;
+            unsigned boff = (unsigned)(((((int64_t)(rhs_ok ? rhs : 0) * 3) * A.nalm + base + l0 + 4 + k) * 2 + ri) * 8);
             wave_sync();
-            int cs = 0;
-            for (; l0 + 7 <= lend; l0 += 4, q ^= 1, cs ^= 1, bq += 8) {
+            // one round with tile Q (products) and Q ^ 1 (the next degrees);
+            // two rounds per loop trip, so that the tile and slot addresses
+            // are fixed
+            auto steady = [&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
                 T b[3], bs[3];
                 operands(braw, b, bs);
                 // the in-flight group (degrees l0 + 8 ..) to the other slot,
                 // then the group after it, then the next B operands
-                cofw[wv][cs ^ 1][lane] = creg;
+                cofw[wv][Q ^ 1][lane] = creg;
                 creg = coef_fetch(cf, l0 + 12, lmax, lane, 4);
-                braw[0] = bq[0];
-                braw[1] = bq[fst];
-                braw[2] = bq[2 * fst];
-                bsyn_mfma<T, PW>(tile[q], k, row, b, bs, acc);
+                braw[0] = *reinterpret_cast<const double*>(sb0 + boff);
+                braw[1] = *reinterpret_cast<const double*>(sb0 + fbytes + boff);
+                braw[2] = *reinterpret_cast<const double*>(sb0 + 2 * fbytes + boff);
+                bsyn_mfma<T, PW>(tile[Q], k, row, b, bs, acc);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    rec_advance(coef_lds(&cofw[wv][cs][j * kCoefN]), s);
-                    syn_store<T, PW>(tile[q ^ 1], j, me, s.l1, s.w1, s.q1);
+                    rec_advance(coef_lds(&cofw[wv][Q][j * kCoefN]), s);
+                    syn_store<T, PW>(tile[Q ^ 1], j, me, s.l1, s.w1, s.q1);
                 }
                 wave_sync();
+                l0 += 4;
+                boff += 64;
+            };
+            if (q == 1) {
+                steady(std::integral_constant<int, 1>());
+                q = 0;
+            }
+            for (; l0 + 11 <= lend;) {
+                steady(std::integral_constant<int, 0>());
+                steady(std::integral_constant<int, 1>());
+            }
+            if (l0 + 7 <= lend) {
+                steady(std::integral_constant<int, 0>());
+                q = 1;
             }
         }
         // tail
