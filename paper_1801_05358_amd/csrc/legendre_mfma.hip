@@ -514,7 +514,7 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
 // C_S = sum A_S G_S with A_S = (lam, q, p) unsigned, and a round's output
 // row l is C_N + eps_l C_S.  Each wave's tile holds one round: the matrix
 // products read it, then the recursion overwrites it with the next round.
-// The waves' outputs are summed in LDS (FP64) one round late, and one
+// The waves' outputs are summed in LDS one round late, and one
 // partial-sum slot per block goes to the combine kernel.
 // ---------------------------------------------------------------------------
 constexpr int kAnaPW = 64;                              // ring pairs per wave
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
 #pragma unroll
     for (int v = 0; v < 4; ++v) sg[v] = ((lo + Mfma<T>::row(lane, v) + m) & 1) ? (T)-1 : (T)1;
 
-    // sum over the waves (FP64) of the round that started at degree l0,
+    // sum over the waves of the round that started at degree l0,
     // held in red[qb], into the block's slot; element e of the round's
     // 3 x 8 x 16 x 2 outputs is re/im e & 1, degree (e >> 1) & 15, rhs
     // (e >> 5) & 7 and field e >> 8, so that each run of 32 threads writes
@@ -663,9 +663,11 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
             const int e = threadIdx.x + k * 64 * W;
             const int ri2 = e & 1, r = (e >> 1) & 15, rr = (e >> 5) & 7, f = e >> 8;
             const int ofs = f * kRedF + (2 * rr + ri2) * kRedCol + r;
-            double sum = 0.0;
+            // in the products' own precision: FP32 on the mixed path, whose
+            // slots hold FP32 anyway (the combine sums the slots in FP64)
+            T sum = red[qb][0][ofs];
 #pragma unroll
-            for (int w2 = 0; w2 < W; ++w2) sum += (double)red[qb][w2][ofs];
+            for (int w2 = 1; w2 < W; ++w2) sum += red[qb][w2][ofs];
             const int l = l0 + r;
             if (l <= lend && rb + rr < nrhs)
                 out[((int64_t)((rb + rr) * 3 + f) * A.nalm + base + l) * 2 + ri2] = (PT)sum;
