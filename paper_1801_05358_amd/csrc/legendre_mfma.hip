@@ -606,6 +606,10 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
 
     const int nrhs = A.nrhs;
     PT* out = partial + ((int64_t)bp.x * nrhs * 3) * A.nalm * 2;
+    // this column tile's part of the slot (a uniform base; lanes add 32-bit
+    // byte offsets, below 2^32 for up to 8 RHS x 3 fields of nalm complex)
+    char* const outb = reinterpret_cast<char*>(out + (int64_t)rb * 3 * A.nalm * 2);
+    const unsigned nal = (unsigned)A.nalm;
     // degrees below the block's first start degree lo are not written: the
     // combine kernel reads this slot from lo on (the slot start table)
     if (lo > lend) return;
@@ -670,7 +674,8 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
             for (int w2 = 1; w2 < W; ++w2) sum += red[qb][w2][ofs];
             const int l = l0 + r;
             if (l <= lend && rb + rr < nrhs)
-                out[((int64_t)((rb + rr) * 3 + f) * A.nalm + base + l) * 2 + ri2] = (PT)sum;
+                *reinterpret_cast<PT*>(outb + (((unsigned)(rr * 3 + f) * nal + (unsigned)(base + l)) * 2u + ri2) *
+                                                  (unsigned)sizeof(PT)) = (PT)sum;
         }
     };
 
@@ -688,7 +693,11 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
     }
     __syncthreads();
     int q = 0, l0 = lo;
-    auto round = [&](auto mode) {
+    // one round; QC >= 0 fixes the slot parity q at compile time (the
+    // steady loop's rounds, two per trip), QC = -1 takes it from q
+    auto round = [&](auto mode, auto qc) {
+        constexpr int QC = decltype(qc)::value;
+        const int qr = QC >= 0 ? QC : q;
         v4 CN[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
         v4 CS[3] = {v4{0, 0, 0, 0}, v4{0, 0, 0, 0}, v4{0, 0, 0, 0}};
         // the north K step st and the mirror one st + KH read the same tile
@@ -711,31 +720,49 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
         if (kMode != 2 && wv == 0) {
             // publish the next round's coefficients (visible after this
             // round's barrier), fetch the ones after them
-            cofb[q ^ 1][lane] = creg0;
+            cofb[qr ^ 1][lane] = creg0;
             creg0 = coef_fetch(cf, l0 + 48, lmax, lane, 16);
         }
         // the products have read the tile (LDS operations of a wave
         // complete in order): the next round's recursion overwrites it
         if constexpr (kMode == 1) {
             if (l0 + 16 <= lend) {
-                if (l0 + 16 <= hi_w) produce(l0 + 16, q, mode);
-                else produce(l0 + 16, q, std::integral_constant<int, 0>());
+                if (l0 + 16 <= hi_w) produce(l0 + 16, qr, mode);
+                else produce(l0 + 16, qr, std::integral_constant<int, 0>());
             }
         } else {
-            if (l0 + 16 <= lend) produce(l0 + 16, q, mode);
+            if (l0 + 16 <= lend) produce(l0 + 16, qr, mode);
         }
-        if (l0 > lo) reduce(l0 - 16, q ^ 1);
+        if (l0 > lo) reduce(l0 - 16, qr ^ 1);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                red[q][wv][f * kRedF + col * kRedCol + Mfma<T>::row(lane, v)] = CN[f][v] + sg[v] * CS[f][v];
+                red[qr][wv][f * kRedF + col * kRedCol + Mfma<T>::row(lane, v)] = CN[f][v] + sg[v] * CS[f][v];
         __syncthreads();
     };
+    using Qrt = std::integral_constant<int, -1>;
+    using Q0 = std::integral_constant<int, 0>;
+    using Q1 = std::integral_constant<int, 1>;
     // rounds whose successor has lanes starting in it
-    for (; l0 + 16 <= hi && l0 + 31 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 1>());
-    for (; l0 + 31 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 0>());
-    for (; l0 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 2>());
+    for (; l0 + 16 <= hi && l0 + 31 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 1>(), Qrt());
+    // steady rounds, two per trip (slot parity 0 then 1)
+    if (q == 1 && l0 + 31 <= lend) {
+        round(std::integral_constant<int, 0>(), Q1());
+        l0 += 16;
+        q = 0;
+    }
+    for (; l0 + 47 <= lend; l0 += 16) {
+        round(std::integral_constant<int, 0>(), Q0());
+        l0 += 16;
+        round(std::integral_constant<int, 0>(), Q1());
+    }
+    if (l0 + 31 <= lend) {
+        round(std::integral_constant<int, 0>(), Q0());
+        l0 += 16;
+        q = 1;
+    }
+    for (; l0 <= lend; l0 += 16, q ^= 1) round(std::integral_constant<int, 2>(), Qrt());
     // the last round's sum
     reduce(l0 - 16, q ^ 1);
 }
