@@ -74,3 +74,21 @@ def test_ring_lds_model_counts_passes():
     assert bench.ring_lds_bytes(2048, 4096, 8) is None
     rr, wr = bench.lds_rates()
     assert 1e13 < wr < rr < 2e14
+
+
+def test_field_errors_find_the_worst_bin():
+    """The accuracy record: a relative perturbation of 1e-3 on degrees >= 128
+    of one RHS's B field is the worst 64-wide bin (starting at 128) with error
+    1e-3; the other fields are exact."""
+    import numpy as np
+    lmax = 130
+    nalm = (lmax + 1) * (lmax + 2) // 2
+    rng = np.random.default_rng(0)
+    ref = rng.standard_normal((2, 3, nalm)) + 1j * rng.standard_normal((2, 3, nalm))
+    x = ref.copy()
+    ls = np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)])
+    x[1, 2, ls >= 128] *= 1 + 1e-3
+    tot, worst, where = bench.field_errors(x, ref, nalm, lmax)
+    assert tot[:2] == [0.0, 0.0] and 0 < tot[2] < 1e-3
+    assert worst[:2] == [0.0, 0.0] and abs(worst[2] - 1e-3) < 1e-12
+    assert where[2] == 128
