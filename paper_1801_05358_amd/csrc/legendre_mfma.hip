@@ -306,7 +306,9 @@ __device__ __forceinline__ void bsyn_mfma(const SynTile<T, PW>& tl, int k, int r
     }
 }
 
-template <typename T, int PW, int kSynWaves>
+// OffT: the lanes' byte offsets from uniform bases (unsigned where they
+// stay below 2^32, see offsets_fit; 64-bit otherwise)
+template <typename T, int PW, int kSynWaves, typename OffT>
 __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const double2* __restrict__ spin,
                                                               T* __restrict__ phase) {
     typedef typename Mfma<T>::v4 v4;
@@ -398,11 +400,12 @@ __global__ __launch_bounds__(64 * kSynWaves) void bsyn_kernel(BatchArgs A, const
             cofw[wv][q][lane] = coef_fetch(cf, l0 + 4, lmax, lane, 4);
             double creg = coef_fetch(cf, l0 + 8, lmax, lane, 4);
             // B operands of the next round (degree l0 + 4 + k <= lend: no
-            // clamp): three uniform field bases and one 32-bit byte offset
-            // per lane, advanced by 4 degrees per round
-            const char* __restrict__ sb0 = reinterpret_cast<const char*>(spin);
+            // clamp): three uniform field bases at this column tile's first
+            // RHS and one byte offset per lane (at most 7 RHS x 3 fields + 1
+            // of nalm complex past the base), advanced by 4 degrees per round
+            const char* __restrict__ sb0 = reinterpret_cast<const char*>(spin + (int64_t)rb * 3 * A.nalm);
             const int64_t fbytes = A.nalm * 16;
-            unsigned boff = (unsigned)(((((int64_t)(rhs_ok ? rhs : 0) * 3) * A.nalm + base + l0 + 4 + k) * 2 + ri) * 8);
+            OffT boff = (OffT)(((((int64_t)(rhs_ok ? rhs - rb : 0) * 3) * A.nalm + base + l0 + 4 + k) * 2 + ri) * 8);
             wave_sync();
             // one round with tile Q (products) and Q ^ 1 (the next degrees);
             // two rounds per loop trip, so that the tile and slot addresses
@@ -539,7 +542,7 @@ __device__ __forceinline__ void rec_act(const BatchArgs& A, const double* __rest
 
 // PT: the partial-sum slots' type (FP32 on the mixed path, where the
 // products are FP32 already; the combine kernel sums the slots in FP64)
-template <typename T, int W, typename PT>
+template <typename T, int W, typename PT, typename OffT>
 __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(BatchArgs A, const typename Vec2<T>::t* __restrict__ phase,
                                                       const double* __restrict__ pair_w,
                                                       PT* __restrict__ partial) {
@@ -606,10 +609,10 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
 
     const int nrhs = A.nrhs;
     PT* out = partial + ((int64_t)bp.x * nrhs * 3) * A.nalm * 2;
-    // this column tile's part of the slot (a uniform base; lanes add 32-bit
-    // byte offsets, below 2^32 for up to 8 RHS x 3 fields of nalm complex)
+    // this column tile's part of the slot (a uniform base; lanes add byte
+    // offsets within 8 RHS x 3 fields of nalm complex)
     char* const outb = reinterpret_cast<char*>(out + (int64_t)rb * 3 * A.nalm * 2);
-    const unsigned nal = (unsigned)A.nalm;
+    const OffT nal = (OffT)A.nalm;
     // degrees below the block's first start degree lo are not written: the
     // combine kernel reads this slot from lo on (the slot start table)
     if (lo > lend) return;
@@ -674,8 +677,8 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 4 ? 2 : 1) void bana_kernel(Ba
             for (int w2 = 1; w2 < W; ++w2) sum += red[qb][w2][ofs];
             const int l = l0 + r;
             if (l <= lend && rb + rr < nrhs)
-                *reinterpret_cast<PT*>(outb + (((unsigned)(rr * 3 + f) * nal + (unsigned)(base + l)) * 2u + ri2) *
-                                                  (unsigned)sizeof(PT)) = (PT)sum;
+                *reinterpret_cast<PT*>(outb + (((OffT)(rr * 3 + f) * nal + (OffT)(base + l)) * 2u + (OffT)ri2) *
+                                                  (OffT)sizeof(PT)) = (PT)sum;
         }
     };
 
@@ -825,16 +828,27 @@ hipError_t launch_slot_starts(dm_plan* p, int* slot_lo, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int W>
-void launch_bsyn_w(dm_plan* p, BatchArgs A, int nrhs, const double2* sp, void* phase, hipStream_t s) {
+// 32-bit lane offsets hold when a column tile's 8 RHS x 3 fields of nalm
+// complex FP64 values (the largest span a lane addresses from its uniform
+// base) stay below 2^32 bytes: lmax <= 4727
+static bool offsets_fit(dm_plan* p) { return (uint64_t)24 * (uint64_t)p->nalm * 16 < ((uint64_t)1 << 32); }
+
+template <int W, typename OffT>
+void launch_bsyn_wo(dm_plan* p, BatchArgs A, int nrhs, const double2* sp, void* phase, hipStream_t s) {
     const int pw = p->precision == DM_MIXED ? 64 : 32;
     A.nx = (p->npairs + pw * W - 1) / (pw * W);
     dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
     dim3 block(64 * W);
     if (p->precision == DM_MIXED)
-        hipLaunchKernelGGL((bsyn_kernel<float, 64, W>), grid, block, 0, s, A, sp, static_cast<float*>(phase));
+        hipLaunchKernelGGL((bsyn_kernel<float, 64, W, OffT>), grid, block, 0, s, A, sp, static_cast<float*>(phase));
     else
-        hipLaunchKernelGGL((bsyn_kernel<double, 32, W>), grid, block, 0, s, A, sp, static_cast<double*>(phase));
+        hipLaunchKernelGGL((bsyn_kernel<double, 32, W, OffT>), grid, block, 0, s, A, sp, static_cast<double*>(phase));
+}
+
+template <int W>
+void launch_bsyn_w(dm_plan* p, BatchArgs A, int nrhs, const double2* sp, void* phase, hipStream_t s) {
+    if (offsets_fit(p)) launch_bsyn_wo<W, unsigned>(p, A, nrhs, sp, phase, s);
+    else launch_bsyn_wo<W, uint64_t>(p, A, nrhs, sp, phase, s);
 }
 
 hipError_t launch_bsyn(dm_plan* p, int nrhs, const double* spin, void* phase, hipStream_t s) {
@@ -854,11 +868,18 @@ hipError_t launch_bana(dm_plan* p, int nrhs, const void* phase, const double* pa
     A.nx = batched_analysis_slots(p);
     A.mchunk = p->ana_mchunk;
     dim3 grid(grid_blocks(A.nx, p->mmax, A.mchunk), (nrhs + 7) / 8);
-    if (p->precision == DM_MIXED)
-        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves, float>), grid, dim3(64 * kAnaWaves), 0, s, A,
+    const bool fit = offsets_fit(p);
+    if (p->precision == DM_MIXED && fit)
+        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves, float, unsigned>), grid, dim3(64 * kAnaWaves), 0, s, A,
                            static_cast<const float2*>(phase), pair_w, reinterpret_cast<float*>(partial));
+    else if (p->precision == DM_MIXED)
+        hipLaunchKernelGGL((bana_kernel<float, kAnaWaves, float, uint64_t>), grid, dim3(64 * kAnaWaves), 0, s, A,
+                           static_cast<const float2*>(phase), pair_w, reinterpret_cast<float*>(partial));
+    else if (fit)
+        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves, double, unsigned>), grid, dim3(64 * kAnaWaves), 0, s, A,
+                           static_cast<const double2*>(phase), pair_w, partial);
     else
-        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves, double>), grid, dim3(64 * kAnaWaves), 0, s, A,
+        hipLaunchKernelGGL((bana_kernel<double, kAnaWaves, double, uint64_t>), grid, dim3(64 * kAnaWaves), 0, s, A,
                            static_cast<const double2*>(phase), pair_w, partial);
     return hipGetLastError();
 }
