@@ -1192,16 +1192,24 @@ dm_status dm_plan_create(dm_plan** out, const dm_grid* grid, int lmax, int max_r
         const size_t B = (size_t)max_rhs;
         dalloc(p, p->d_phase, B * 3 * p->npairs * (p->mmax + 1) * 4);
         if (precision == DM_MIXED) dalloc(p, p->d_phase32, B * 3 * p->npairs * (p->mmax + 1) * 4);
-        // partial-sum slots for every kernel the plan may run (a mixed plan
-        // also runs the FP64 batched kernels for its FP64 epilogue)
-        size_t slots = (size_t)std::max(p->ana_chunks, batched_analysis_slots(p));
+        // partial-sum slots for every analysis the plan may run: a call of n
+        // RHS takes a slot set of n RHS per slot, from the batched kernels'
+        // slots or the vector kernel's chunks (which of the two runs depends
+        // on n); a mixed plan also runs the FP64 kernels for its FP64
+        // epilogue
+        size_t slot_rhs = 0;
         {
             const dm_precision pr = p->precision;
-            p->precision = DM_FP64;
-            slots = std::max(slots, (size_t)batched_analysis_slots(p));
+            for (dm_precision q : {pr, DM_FP64}) {
+                p->precision = q;
+                for (size_t n : {B, std::min(B, (size_t)7), (size_t)1}) {
+                    const size_t ns = use_mfma(p, (int)n) ? (size_t)batched_analysis_slots(p) : (size_t)p->ana_chunks;
+                    slot_rhs = std::max(slot_rhs, ns * n);
+                }
+            }
             p->precision = pr;
         }
-        dalloc(p, p->d_partial, slots * B * 3 * p->nalm * 2);
+        dalloc(p, p->d_partial, slot_rhs * 3 * p->nalm * 2);
         dalloc(p, p->d_alm, B * 3 * p->nalm * 2);
         dalloc(p, p->d_alm_prev, B * 3 * p->nalm * 2);
         dalloc(p, p->d_state_u, B * 3 * p->nalm * 2);
