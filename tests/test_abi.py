@@ -122,3 +122,21 @@ def test_binding_refuses_two_hip_runtimes():
                        timeout=600)
     assert r.returncode == 0, r.stderr
     assert r.stdout.startswith("refused") and "two HIP runtimes" in r.stdout, r.stdout
+
+
+def test_environment_variables_are_documented():
+    """Every DMWF_* variable the library reads is listed in the header's
+    account of plan creation, and nothing listed there is unread."""
+    csrc = os.path.join(ROOT, "paper_1801_05358_amd", "csrc")
+    read = set()
+    for f in os.listdir(csrc):
+        if f.endswith((".cpp", ".hip", ".h")):
+            txt = open(os.path.join(csrc, f)).read()
+            read |= set(re.findall(r'(?:env_int|getenv)\("(DMWF_[A-Z0-9_]+)"', txt))
+    header = open(HEADER).read()
+    listed = set(re.findall(r"^ \*\s+(DMWF_[A-Z0-9_]+)", header, flags=re.M))
+    listed |= set(re.findall(r",\s+(DMWF_[A-Z0-9_]+)", " ".join(
+        l for l in header.splitlines() if l.startswith(" *   DMWF_"))))
+    assert read, "no environment reads found"
+    assert read <= listed, f"read but not documented: {sorted(read - listed)}"
+    assert listed <= read, f"documented but not read: {sorted(listed - read)}"
